@@ -1,0 +1,223 @@
+/*
+ * qpe.h -- C ABI of the MI355X (gfx950) QPE statevector emulator.
+ *
+ * Operation (paper section 2, Fig. 1, the QPE circuit): for a target matrix
+ * U (d x d, d = 2^N_mat), an input state psi (d) and N_meas measurement
+ * qubits (N = 2^N_meas), return the measurement probabilities
+ *
+ *     A[m, :] = 2^-N_meas * sum_{j<N} exp(-2 pi i j m / N) U^j psi
+ *     P(m)    = sum_r |A[m, r]|^2,         m = 0 .. N-1.
+ *
+ * The circuit: H on every measurement qubit of |0..0>, then for k = 0..n-1
+ * the qubit carrying bit k of the register integer controls U^(2^k), then the
+ * inverse QFT on the measurement register, then measurement. The readout is
+ * the "norm of the final statevector" of the paper (section 3) marginalised
+ * over the target register. Bit k of the outcome m is the qubit that
+ * controlled U^(2^k); the peak of an eigenvector input with eigenphase phi
+ * lies at m ~ phi * N.
+ *
+ * Conventions common to every entry point:
+ *  - complex128 = two doubles (re, im), complex64 = two floats (re, im);
+ *    matrices are row-major: (U v)_r = sum_c U[r*d + c] v_c.
+ *  - Every data pointer is a DEVICE pointer owned by the caller; the library
+ *    never allocates or frees device memory. Scratch memory comes from the
+ *    caller's workspace (size from qpe_workspace_size), 256-byte aligned.
+ *  - Work is enqueued asynchronously on the context's HIP stream; results are
+ *    valid after the caller synchronises that stream. A call returns before
+ *    the device work is done, so device faults surface as QPE_ERR_HIP from a
+ *    later call.
+ *  - Argument, size and alignment checks run on the host before any HIP call
+ *    and need no device. No function aborts and no C++ exception crosses the
+ *    ABI. On error nothing has been enqueued.
+ *  - Not thread-safe per context; distinct contexts are independent.
+ */
+#ifndef QPE_H
+#define QPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum qpe_status {
+  QPE_OK = 0,
+  QPE_ERR_ARG = 1,         /* null pointer, unknown form/flag, bad count   */
+  QPE_ERR_SIZE = 2,        /* N_meas / N_mat (or a GEMM size) out of range */
+  QPE_ERR_ALIGN = 3,       /* a device pointer is not 16-byte aligned       */
+  QPE_ERR_WORKSPACE = 4,   /* workspace null, too small or not 256-aligned */
+  QPE_ERR_OOM = 5,         /* host allocation for the context failed       */
+  QPE_ERR_NO_DEVICE = 6,   /* no HIP device, or the device index is invalid*/
+  QPE_ERR_HIP = 7,         /* a HIP runtime call or a kernel launch failed */
+  QPE_ERR_UNSUPPORTED = 8  /* valid request this build does not implement  */
+} qpe_status;
+
+/* Arithmetic form of the statevector path.
+ *  QPE_FORM_FP64 : complex128 state; FP64 matrix-core GEMMs throughout.
+ *  QPE_FORM_MIXED: complex64 state; the controlled products run as split
+ *                  BF16 matrix-core products (three BF16 pieces of each
+ *                  operand, six partial products) accumulated in FP32; the
+ *                  inverse QFT runs in FP32 and the readout sums in FP64.
+ * In both forms the powers U^(2^k) are formed in FP64. */
+typedef enum qpe_form { QPE_FORM_FP64 = 0, QPE_FORM_MIXED = 1 } qpe_form;
+
+/* Run flags. */
+enum {
+  /* Skip the Newton-Schulz re-unitarisation of the powers. Required when U
+   * is not unitary (the paper's analytic test problem, section 3, builds
+   * U = P Lambda P^-1 with a non-unitary P). */
+  QPE_NO_POLAR = 1u << 0
+};
+
+/* Report flags (qpe_report.flags). */
+enum {
+  QPE_REPORT_NOT_UNITARY = 1u << 0, /* max|V^H V - I| above 1e-6 at some step */
+  QPE_REPORT_NUMERIC = 1u << 1      /* NaN/Inf in P, or |sum P - |psi|^2| > 1e-4*|psi|^2 */
+};
+
+/* Limits. d = 2^n_mat, N = 2^n_meas. */
+#define QPE_MAX_N_MEAS 30
+#define QPE_MAX_N_MAT 15
+#define QPE_MAX_TOTAL_QUBITS 34 /* n_meas + n_mat */
+
+/* One QPE instance. U: device complex128 [d*d]; psi: device complex128 [d]
+ * (not renormalised: sum_m P(m) = ||psi||^2 up to rounding); prob: device
+ * float64 [N], written. U and psi are read only. */
+typedef struct qpe_problem {
+  int32_t n_meas; /* 1 .. QPE_MAX_N_MEAS                       */
+  int32_t n_mat;  /* 0 .. QPE_MAX_N_MAT                        */
+  const void *U;
+  const void *psi;
+  double *prob;
+} qpe_problem;
+
+/* Device-written diagnostics, one per instance (caller-owned device memory,
+ * 8-byte aligned). unitarity_defect is the largest max-norm of V^H V - I met
+ * before each Newton-Schulz step (0 when QPE_NO_POLAR); prob_sum = sum_m P(m);
+ * psi_norm2 = ||psi||^2. */
+typedef struct qpe_report {
+  double unitarity_defect;
+  double prob_sum;
+  double psi_norm2;
+  uint32_t flags;
+  uint32_t reserved;
+} qpe_report;
+
+typedef struct qpe_ctx qpe_ctx;
+
+/* Create a context bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t; NULL = the legacy default stream). Host memory only.
+ * Errors: QPE_ERR_ARG (ctx NULL), QPE_ERR_NO_DEVICE, QPE_ERR_OOM. */
+qpe_status qpe_ctx_create(qpe_ctx **ctx, int device, void *stream);
+
+/* Rebind the context to another stream on the same device. */
+qpe_status qpe_ctx_set_stream(qpe_ctx *ctx, void *stream);
+
+/* Destroy a context (host memory only; does not synchronise). NULL is OK. */
+qpe_status qpe_ctx_destroy(qpe_ctx *ctx);
+
+/* Workspace bytes qpe_run needs for these problems, form and flags. Only the
+ * size fields of the problems are read (pointers may be NULL). Host only.
+ * Errors: QPE_ERR_ARG, QPE_ERR_SIZE. */
+qpe_status qpe_workspace_size(const qpe_problem *problems, int count, int form,
+                              unsigned flags, size_t *bytes);
+
+/* Run `count` independent QPE instances (paper section 2, Fig. 1) and write
+ * each instance's probability vector. problems: HOST array of `count`
+ * entries. workspace: device, >= qpe_workspace_size bytes, 256-aligned; its
+ * contents on entry are ignored. report: device array of `count` qpe_report,
+ * or NULL. count > 1 runs the instances batched (uneven sizes allowed).
+ * Nothing is allocated; the call is asynchronous on the context stream and
+ * may be captured in a HIP graph.
+ * Errors: QPE_ERR_ARG, QPE_ERR_SIZE, QPE_ERR_ALIGN, QPE_ERR_WORKSPACE,
+ * QPE_ERR_HIP. */
+qpe_status qpe_run(qpe_ctx *ctx, const qpe_problem *problems, int count, int form,
+                   unsigned flags, void *workspace, size_t workspace_bytes,
+                   qpe_report *report);
+
+/* Host-only pre-flight: the status qpe_run would return for these arguments
+ * before it touches the context or the device (QPE_OK if they are valid).
+ * Never dereferences device pointers. */
+qpe_status qpe_check_run(const qpe_problem *problems, int count, int form, unsigned flags,
+                         const void *workspace, size_t workspace_bytes, const void *report);
+
+/* ---- stage entry points (one step of the path each, for per-step checks) ---- */
+
+/* Powers of U (the controlled operators of Fig. 1): V_k = U^(2^k) for
+ * k = 0 .. count_k-1, by FP64 repeated squaring, each square followed by one
+ * Newton-Schulz step X <- X (3I - X^H X)/2 unless QPE_NO_POLAR.
+ * U: device complex128 [d*d]; V_out: device complex128 [count_k][d][d];
+ * workspace: >= qpe_powers_workspace_size bytes; report: device qpe_report
+ * or NULL (only unitarity_defect is written). 1 <= count_k <= 30. */
+qpe_status qpe_powers_workspace_size(int n_mat, size_t *bytes);
+qpe_status qpe_powers(qpe_ctx *ctx, int n_mat, const void *U, int count_k,
+                      unsigned flags, void *V_out, void *workspace,
+                      size_t workspace_bytes, qpe_report *report);
+
+/* One controlled step of Fig. 1 on a caller-held state: for every row j of
+ * state (N x d, row-major) whose bit k is set, state[j,:] <- state[j,:] V^T
+ * (i.e. the target vector s becomes V s). V: device complex128 [d*d]. state:
+ * complex128 (QPE_FORM_FP64) or complex64 (QPE_FORM_MIXED), updated in place.
+ * Uses the same operator preparation and GEMM kernels as qpe_run.
+ * 0 <= k < n_meas. workspace >= qpe_controlled_step_workspace_size. */
+qpe_status qpe_controlled_step_workspace_size(int n_meas, int n_mat, int form, size_t *bytes);
+qpe_status qpe_controlled_step(qpe_ctx *ctx, int n_meas, int n_mat, int form, int k,
+                               const void *V, void *state, void *workspace,
+                               size_t workspace_bytes);
+
+/* Inverse QFT on the measurement register followed by the readout (the last
+ * two stages of Fig. 1): state (N x d, complex128 for FP64, complex64 for
+ * MIXED) is transformed in place into a digit-reversed row order (contents
+ * unspecified afterwards) and prob[m] = sum_r |A[m, r]|^2 is written
+ * (device float64 [N]). workspace >= qpe_iqft_workspace_size. */
+qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size_t *bytes);
+qpe_status qpe_iqft_probs(qpe_ctx *ctx, int n_meas, int n_mat, int form, void *state,
+                          double *prob, void *workspace, size_t workspace_bytes);
+
+/* Complex FP64 GEMM on the matrix cores (the building block of the powers):
+ * C = alpha * op(A) * op(B) + beta * Cin, op in {'N','T','C'} (none,
+ * transpose, conjugate transpose); op(A) is M x K, op(B) is K x N; all
+ * complex128 row-major with leading dimensions lda/ldb/ldc in elements.
+ * alpha/beta: complex (re, im) pairs. Cin may equal C (then read before
+ * write per element) or be NULL when beta == 0. 1 <= M, N, K <= 65536. */
+qpe_status qpe_zgemm(qpe_ctx *ctx, char opA, char opB, int M, int N, int K,
+                     const double *alpha, const void *A, int lda, const void *B, int ldb,
+                     const double *beta, const void *Cin, int ldcin, void *C, int ldc);
+
+/* ---- per-kernel timing (HIP events on the context stream) ----
+ * When enabled, every launch of the kernel classes below is bracketed by a
+ * pair of HIP events recorded on the context stream (a pool of `max_pairs`
+ * pairs is created on the host by the enable call; launches beyond the pool
+ * go untimed). qpe_ctx_read_timing synchronises the recorded events and
+ * returns the number of timed launches of a class and their summed
+ * duration. Resetting frees the pool for reuse. Not capturable. */
+enum {
+  QPE_TIMER_CTRL_GEMM = 0, /* controlled-step kernels (all forms)          */
+  QPE_TIMER_POWERS = 1,    /* FP64 squaring and Newton-Schulz kernels       */
+  QPE_TIMER_SPLIT = 2,     /* operator split into BF16 planes              */
+  QPE_TIMER_QFT = 3,       /* inverse-DFT passes                           */
+  QPE_TIMER_PROB = 4,      /* readout                                      */
+  QPE_TIMER_HLAYER = 5,    /* Hadamard layer                               */
+  QPE_TIMER_COUNT = 6
+};
+qpe_status qpe_ctx_enable_timing(qpe_ctx *ctx, int max_pairs);
+qpe_status qpe_ctx_reset_timing(qpe_ctx *ctx);
+qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *total_ms);
+
+/* ---- misc ---- */
+
+/* Static text for a status code (never NULL). */
+const char *qpe_status_string(int status);
+
+/* Text of the most recent error on this context (HIP error name included),
+ * or "" if none. Valid until the next call on ctx. */
+const char *qpe_last_error(const qpe_ctx *ctx);
+
+/* Library version, "major.minor.patch". */
+const char *qpe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPE_H */

@@ -1,0 +1,311 @@
+// Bandwidth-bound kernels of the QPE path: Hadamard layer, twiddle tables,
+// operator split into BF16 pieces, Newton-Schulz identity subtraction with
+// the unitarity defect, probability readout and the per-run report.
+#include "qpe_internal.hpp"
+
+#include <cmath>
+
+namespace qpe {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(int64_t work, int per_block = kThreads, int cap = 256 * 64) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+// H on every qubit of |0...0> gives the uniform superposition, so every row
+// of the (N x d) state becomes psi * 2^(-n/2) (Fig. 1, H layer).
+__global__ void __launch_bounds__(kThreads) k_h_broadcast_c64(const double2* __restrict__ psi,
+                                                              float4* __restrict__ out, int64_t pairs,
+                                                              int dmask, double scale) {
+  for (int64_t q = blockIdx.x * int64_t(kThreads) + threadIdx.x; q < pairs;
+       q += int64_t(gridDim.x) * kThreads) {
+    double2 a = psi[(2 * q) & dmask];
+    double2 b = psi[(2 * q + 1) & dmask];
+    out[q] = make_float4(float(a.x * scale), float(a.y * scale), float(b.x * scale), float(b.y * scale));
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_h_broadcast_c128(const double2* __restrict__ psi,
+                                                               double2* __restrict__ out, int64_t total,
+                                                               int dmask, double scale) {
+  for (int64_t q = blockIdx.x * int64_t(kThreads) + threadIdx.x; q < total;
+       q += int64_t(gridDim.x) * kThreads) {
+    double2 a = psi[q & dmask];
+    out[q] = make_double2(a.x * scale, a.y * scale);
+  }
+}
+
+// tw_lo[t] = exp(-2 pi i t / N) for t < 2^h; tw_hi[u] = exp(-2 pi i u 2^h / N).
+// The angle -2 t / N (in units of pi) is exact in binary.
+__global__ void __launch_bounds__(kThreads) k_twiddles(double2* __restrict__ tw_hi, double2* __restrict__ tw_lo,
+                                                       int n, int h) {
+  int64_t nlo = int64_t(1) << h, nhi = int64_t(1) << (n - h);
+  for (int64_t t = blockIdx.x * int64_t(kThreads) + threadIdx.x; t < nlo + nhi;
+       t += int64_t(gridDim.x) * kThreads) {
+    int64_t e = t < nlo ? t : ((t - nlo) << h);
+    double x = -std::ldexp(double(e), 1 - n);  // -2 e / N
+    double sv, cv;
+    sincospi(x, &sv, &cv);
+    if (t < nlo)
+      tw_lo[t] = make_double2(cv, sv);
+    else
+      tw_hi[t - nlo] = make_double2(cv, sv);
+  }
+}
+
+// Round a double to the nearest BF16 value (ties to even); returns the BF16
+// bit pattern and the rounded value as a double. Magnitudes here lie far
+// inside the normal range of both formats.
+__device__ inline uint16_t bf16_rne(double x, double* rounded) {
+  if (x == 0.0) {
+    *rounded = 0.0;
+    return 0;
+  }
+  uint64_t b = __double_as_longlong(x);
+  uint64_t lsb = (b >> 45) & 1;
+  b += ((uint64_t(1) << 44) - 1) + lsb;
+  b &= ~((uint64_t(1) << 45) - 1);
+  double y = __longlong_as_double(b);
+  *rounded = y;
+  float f = float(y);  // exact: y has 8 significant bits
+  return uint16_t(__float_as_uint(f) >> 16);
+}
+
+// Operator preparation for the mixed controlled GEMM: the complex FP64
+// matrix V (d x d) is split, per real component w, into three BF16 pieces
+// w = hi + mid + lo (each the RNE rounding of the remaining residual). Plane
+// p = 2 * piece + component (component 0 = real, 1 = imaginary). Inside a
+// plane the layout is blocked by 32 columns: element (row j, col c) sits at
+// ((c / 32) * d + j) * 32 + c % 32, so that a tile of consecutive rows and 32
+// consecutive columns is contiguous.
+__global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
+                                                           int t) {
+  const int64_t d = int64_t(1) << t;
+  const int64_t dd = d * d;
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+    int64_t j = e >> t, c = e & (d - 1);
+    double2 v = V[e];
+    int64_t dst = (((c >> 5) * d + j) << 5) + (c & 31);
+    double w[2] = {v.x, v.y};
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      double r0 = w[comp], q0, q1, q2;
+      uint16_t hi = bf16_rne(r0, &q0);
+      double r1 = r0 - q0;
+      uint16_t mid = bf16_rne(r1, &q1);
+      double r2 = r1 - q1;
+      uint16_t lo = bf16_rne(r2, &q2);
+      planes[(0 * 2 + comp) * dd + dst] = hi;
+      planes[(1 * 2 + comp) * dd + dst] = mid;
+      planes[(2 * 2 + comp) * dd + dst] = lo;
+    }
+  }
+}
+
+// Newton-Schulz support: G <- G - I and defect = max(defect, max |G_ij|).
+// The max of non-negative doubles is order-independent, so the atomic on the
+// IEEE bit pattern (monotone for non-negative values) is deterministic.
+__global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G, int d,
+                                                                  unsigned long long* __restrict__ defect_bits) {
+  __shared__ double red[kThreads / 64];
+  const int64_t dd = int64_t(d) * d;
+  double mx = 0.0;
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+    double2 g = G[e];
+    if ((e / d) == (e % d)) {
+      g.x -= 1.0;
+      G[e] = g;
+    }
+    double a = sqrt(g.x * g.x + g.y * g.y);
+    mx = (a > mx || a != a) ? a : mx;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(mx, off);
+    mx = (o > mx || o != o) ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) mx = (red[w] > mx || red[w] != red[w]) ? red[w] : mx;
+    unsigned long long bits = (unsigned long long)__double_as_longlong(mx != mx ? __longlong_as_double(0x7ff0000000000000ll) : mx);
+    atomicMax(defect_bits, bits);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+// Readout: P(m(p)) = 2^-n sum_r |X[p][r]|^2 in FP64 (components widened
+// before squaring). The DFT passes leave out the inverse QFT's 2^(-n/2), so
+// the exact power-of-two 2^-n restores it here. One row per group of
+// G = min(d, 64) lanes; a fixed shuffle tree makes the sum order
+// deterministic.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prob(const T* __restrict__ X, double* __restrict__ prob, int n, int t,
+                                                   DftPlan plan, double scale) {
+  const int64_t N = int64_t(1) << n;
+  const int d = 1 << t;
+  const int G = d < 64 ? d : 64;
+  const int lane = threadIdx.x & 63;
+  const int rows_per_wave = 64 / G;
+  const int64_t wave = (blockIdx.x * int64_t(kThreads) + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * kThreads) >> 6;
+  for (int64_t base = wave * rows_per_wave; base < N; base += nwaves * rows_per_wave) {
+    int64_t p = base + lane / G;
+    int c0 = lane % G;
+    double acc = 0.0;
+    if (p < N) {
+      const T* row = X + p * d;
+      for (int c = c0; c < d; c += G) {
+        T v = row[c];
+        double re = double(v.x), im = double(v.y);
+        acc += re * re + im * im;
+      }
+    }
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
+  }
+}
+
+// Report: prob_sum, ||psi||^2, the defect, and the flags. One block.
+__global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
+                                                     const double2* __restrict__ psi, int t,
+                                                     const unsigned long long* __restrict__ defect_bits,
+                                                     double* __restrict__ report) {
+  __shared__ double red[2][kThreads];
+  const int64_t N = int64_t(1) << n;
+  const int d = 1 << t;
+  double s = 0.0, q = 0.0;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < N; i += kThreads) {
+    double v = prob[i];
+    bad |= !(v == v) || v > 1e300 || v < -1e300;
+    s += v;
+  }
+  for (int i = threadIdx.x; i < d; i += kThreads) q += psi[i].x * psi[i].x + psi[i].y * psi[i].y;
+  red[0][threadIdx.x] = s;
+  red[1][threadIdx.x] = q;
+  __shared__ int any_bad;
+  if (threadIdx.x == 0) any_bad = 0;
+  __syncthreads();
+  if (bad) atomicOr(&any_bad, 1);
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double defect = defect_bits ? __longlong_as_double((long long)defect_bits[0]) : 0.0;
+    double ps = red[0][0], pn = red[1][0];
+    unsigned flags = 0;
+    if (defect > 1e-6 || defect != defect) flags |= 1u;
+    if (any_bad || !(fabs(ps - pn) <= 1e-4 * pn)) flags |= 2u;
+    report[0] = defect;
+    report[1] = ps;
+    report[2] = pn;
+    reinterpret_cast<uint32_t*>(report + 3)[0] = flags;
+    reinterpret_cast<uint32_t*>(report + 3)[1] = 0u;
+  }
+}
+
+// After a stand-alone controlled step (whole state in buf0, updated rows
+// written to `other`), copy the rows with bit k set back into buf0.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_copy_rows_back(T* __restrict__ state, const T* __restrict__ other, int n,
+                                                             int t, int k) {
+  const int64_t half = (int64_t(1) << (n - 1)) << t;
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < half; e += int64_t(gridDim.x) * kThreads) {
+    int64_t i = e >> t;
+    int64_t c = e & ((int64_t(1) << t) - 1);
+    int64_t j = ctrl_row(i, k);
+    state[(j << t) + c] = other[(j << t) + c];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s) {
+  const int64_t total = int64_t(1) << (n + t);
+  const double scale = std::ldexp(1.0, -(n / 2)) * ((n & 1) ? std::sqrt(0.5) : 1.0);
+  if (mixed) {
+    // total >= 2 because n >= 1
+    int64_t pairs = total / 2;
+    hipLaunchKernelGGL(k_h_broadcast_c64, dim3(grid_for(pairs)), dim3(kThreads), 0, s,
+                       static_cast<const double2*>(psi), static_cast<float4*>(state), pairs, (1 << t) - 1, scale);
+  } else {
+    hipLaunchKernelGGL(k_h_broadcast_c128, dim3(grid_for(total)), dim3(kThreads), 0, s,
+                       static_cast<const double2*>(psi), static_cast<double2*>(state), total, (1 << t) - 1, scale);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s) {
+  int64_t work = (int64_t(1) << h) + (int64_t(1) << (n - h));
+  hipLaunchKernelGGL(k_twiddles, dim3(grid_for(work)), dim3(kThreads), 0, s, tw_hi, tw_lo, n, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s) {
+  int64_t dd = int64_t(1) << (2 * t);
+  hipLaunchKernelGGL(k_split_pieces, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_identity_defect(double2* G, int d, unsigned long long* defect_bits, hipStream_t s) {
+  int64_t dd = int64_t(d) * d;
+  hipLaunchKernelGGL(k_sub_identity_defect, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, G, d,
+                     defect_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
+                       hipStream_t s) {
+  const int64_t N = int64_t(1) << n;
+  const int d = 1 << t;
+  const int G = d < 64 ? d : 64;
+  int64_t waves = (N * G + 63) / 64;
+  int grid = grid_for(waves * 64);
+  const double scale = std::ldexp(1.0, -n);
+  if (mixed)
+    hipLaunchKernelGGL(k_prob<float2>, dim3(grid), dim3(kThreads), 0, s, static_cast<const float2*>(state), prob, n,
+                       t, plan, scale);
+  else
+    hipLaunchKernelGGL(k_prob<double2>, dim3(grid), dim3(kThreads), 0, s, static_cast<const double2*>(state), prob,
+                       n, t, plan, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_report(const double* prob, int n, const double2* psi, int t, const unsigned long long* defect_bits,
+                         void* report, hipStream_t s) {
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, s, prob, n, psi, t, defect_bits,
+                     static_cast<double*>(report));
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows_back(bool mixed, void* state, const void* other, int n, int t, int k, hipStream_t s) {
+  int64_t half = (int64_t(1) << (n - 1)) << t;
+  if (mixed)
+    hipLaunchKernelGGL(k_copy_rows_back<float2>, dim3(grid_for(half)), dim3(kThreads), 0, s,
+                       static_cast<float2*>(state), static_cast<const float2*>(other), n, t, k);
+  else
+    hipLaunchKernelGGL(k_copy_rows_back<double2>, dim3(grid_for(half)), dim3(kThreads), 0, s,
+                       static_cast<double2*>(state), static_cast<const double2*>(other), n, t, k);
+  return hipGetLastError();
+}
+
+}  // namespace qpe

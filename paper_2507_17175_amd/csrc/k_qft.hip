@@ -1,0 +1,250 @@
+// Inverse QFT on the measurement register (Fig. 1, QFT^-1): for every target
+// column r, the unitary inverse DFT of length N = 2^n along the row index,
+//   A[m] = 2^(-n/2) sum_j exp(-2 pi i j m / N) S[j]
+// The passes compute the sum without the 2^(-n/2); the readout applies the
+// exact power of two 2^-n to |A|^2 instead.
+//
+// Decomposition: a sequence of radix-R passes (R = 2^b, b <= 8). Pass q acts
+// on blocks of B = N >> (bits before q) consecutive rows; inside a block, row
+// j = j1 * M + j2 (M = B / R) and for each (j2, column) the R-point DFT over
+// j1 is taken, multiplied by the twiddle exp(-2 pi i j2 m1 / B) and written
+// back in place to row m1 * M + j2. After all passes, row p holds outcome
+// m = digit_reverse(p) (the readout kernel undoes it). The R-point DFT itself
+// is split R = R1 x R2: an R1-point DFT in registers, a twiddle, an exchange
+// through LDS, and an R2-point DFT in registers. Threads own consecutive
+// (j2, column) elements, so every global access is a contiguous run.
+//
+// Twiddles exp(-2 pi i x / N) come from two small FP64 tables indexed by
+// the exact integer x (x = hi * 2^h + lo), multiplied in FP64.
+#include "qpe_internal.hpp"
+
+namespace qpe {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T> struct Real;
+template <> struct Real<float2> { typedef float type; };
+template <> struct Real<double2> { typedef double type; };
+
+// cos and sin of pi k / 8, k = 0..7: omega_16^k = c16(k) - i s16(k).
+__host__ __device__ constexpr double c16(int k) {
+  return k == 0 ? 1.0 : k == 1 ? 0.92387953251128675613 : k == 2 ? 0.70710678118654752440
+       : k == 3 ? 0.38268343236508977173 : k == 4 ? 0.0 : k == 5 ? -0.38268343236508977173
+       : k == 6 ? -0.70710678118654752440 : -0.92387953251128675613;
+}
+__host__ __device__ constexpr double s16(int k) {
+  return k == 0 ? 0.0 : k == 1 ? 0.38268343236508977173 : k == 2 ? 0.70710678118654752440
+       : k == 3 ? 0.92387953251128675613 : k == 4 ? 1.0 : k == 5 ? 0.92387953251128675613
+       : k == 6 ? 0.70710678118654752440 : 0.38268343236508977173;
+}
+
+__host__ __device__ constexpr int brev(int m, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((m >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+template <int P> struct Log2 { static constexpr int v = 1 + Log2<P / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+// In-register radix-2 decimation-in-frequency DFT of P <= 16 points
+// (forward sign). On return re/im[brev(m)] holds output m.
+template <typename R, int P>
+__device__ __forceinline__ void dft_regs(R* re, R* im) {
+#pragma unroll
+  for (int s = P / 2; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int st = 0; st < P; st += 2 * s) {
+#pragma unroll
+      for (int i = 0; i < s; ++i) {
+        R ar = re[st + i], ai = im[st + i], br = re[st + i + s], bi = im[st + i + s];
+        re[st + i] = ar + br;
+        im[st + i] = ai + bi;
+        R dr = ar - br, di = ai - bi;
+        const int kw = i * (8 / s);  // omega_{2s}^i = omega_16^{8 i / s}
+        if (kw == 0) {
+          re[st + i + s] = dr;
+          im[st + i + s] = di;
+        } else if (kw == 4) {
+          re[st + i + s] = di;
+          im[st + i + s] = -dr;
+        } else {
+          const R c = R(c16(kw)), sn = R(s16(kw));
+          re[st + i + s] = dr * c + di * sn;
+          im[st + i + s] = di * c - dr * sn;
+        }
+      }
+    }
+  }
+}
+
+// exp(-2 pi i x / N), x in [0, N), as (cos, sin) in FP64.
+__device__ __forceinline__ double2 twiddle(int64_t x, const double2* __restrict__ tw_hi,
+                                           const double2* __restrict__ tw_lo, int h) {
+  double2 a = tw_hi[x >> h], b = tw_lo[x & ((int64_t(1) << h) - 1)];
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, const T* __restrict__ buf1, int gather,
+                                                       int n, int t, int pass_bits, int bits_before,
+                                                       const double2* __restrict__ tw_hi,
+                                                       const double2* __restrict__ tw_lo, int h) {
+  typedef typename Real<T>::type R;
+  constexpr int E = kThreads / R2;  // elements per workgroup
+  constexpr int L1 = Log2<R1>::v, L2 = Log2<R2>::v;
+  __shared__ T L[R2 > 1 ? R1 * R2 * E : 1];
+
+  const int bq_log = n - bits_before;        // rows per block (log2)
+  const int m_log = bq_log - pass_bits;      // rows between DFT points (log2)
+  const int64_t md = int64_t(1) << (m_log + t);
+  const int64_t total_e = int64_t(1) << (n + t - pass_bits);
+  const int64_t f0 = int64_t(blockIdx.x) * E;
+  const int tid = threadIdx.x;
+
+  auto element = [&](int e, int64_t& base, int64_t& j2) {
+    int64_t f = f0 + e;
+    int64_t blk = f >> (m_log + t), rem = f & (md - 1);
+    j2 = rem >> t;
+    base = (blk << (bq_log + t)) + rem;
+  };
+
+  // Phase A: R1-point DFTs over j1a (j1 = j1a * R2 + j1b).
+  {
+    const int e = tid % E, j1b = tid / E;
+    const bool ok = f0 + e < total_e;
+    int64_t base = 0, j2 = 0;
+    if (ok) element(e, base, j2);
+    R re[R1], im[R1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+      int64_t idx = base + int64_t(a * R2 + j1b) * md;
+      T v;
+      v.x = R(0);
+      v.y = R(0);
+      if (ok) {
+        const T* src = (gather && (__builtin_popcountll(uint64_t(idx >> t)) & 1)) ? buf1 : buf0;
+        v = src[idx];
+      }
+      re[a] = v.x;
+      im[a] = v.y;
+    }
+    dft_regs<R, R1>(re, im);
+    if (R2 == 1) {
+      if (ok) {
+#pragma unroll
+        for (int m1 = 0; m1 < R1; ++m1) {
+          R yr = re[brev(m1, L1)], yi = im[brev(m1, L1)];
+          int64_t x = (j2 * m1) << bits_before;
+          T o;
+          if (x == 0) {
+            o.x = yr;
+            o.y = yi;
+          } else {
+            double2 w = twiddle(x, tw_hi, tw_lo, h);
+            o.x = R(double(yr) * w.x - double(yi) * w.y);
+            o.y = R(double(yr) * w.y + double(yi) * w.x);
+          }
+          buf0[base + int64_t(m1) * md] = o;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int m1a = 0; m1a < R1; ++m1a) {
+        R yr = re[brev(m1a, L1)], yi = im[brev(m1a, L1)];
+        int64_t x = int64_t(j1b * m1a) << (n - pass_bits);
+        T o;
+        if (x == 0) {
+          o.x = yr;
+          o.y = yi;
+        } else {
+          double2 w = twiddle(x, tw_hi, tw_lo, h);
+          o.x = R(double(yr) * w.x - double(yi) * w.y);
+          o.y = R(double(yr) * w.y + double(yi) * w.x);
+        }
+        L[(m1a * R2 + j1b) * E + e] = o;
+      }
+    }
+  }
+  if (R2 == 1) return;
+  __syncthreads();
+
+  // Phase B: R2-point DFTs over j1b, outer twiddle, store.
+  for (int u = tid; u < E * R1; u += kThreads) {
+    const int e = u % E, m1a = u / E;
+    if (f0 + e >= total_e) continue;
+    int64_t base, j2;
+    element(e, base, j2);
+    R re[R2], im[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) {
+      T v = L[(m1a * R2 + b) * E + e];
+      re[b] = v.x;
+      im[b] = v.y;
+    }
+    dft_regs<R, R2>(re, im);
+#pragma unroll
+    for (int m1b = 0; m1b < R2; ++m1b) {
+      const int m1 = m1a + R1 * m1b;
+      R yr = re[brev(m1b, L2)], yi = im[brev(m1b, L2)];
+      int64_t x = (j2 * m1) << bits_before;
+      T o;
+      if (x == 0) {
+        o.x = yr;
+        o.y = yi;
+      } else {
+        double2 w = twiddle(x, tw_hi, tw_lo, h);
+        o.x = R(double(yr) * w.x - double(yi) * w.y);
+        o.y = R(double(yr) * w.y + double(yi) * w.x);
+      }
+      buf0[base + int64_t(m1) * md] = o;
+    }
+  }
+}
+
+template <typename T, int R1, int R2>
+hipError_t go(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
+              const double2* lo, int h, hipStream_t s) {
+  constexpr int E = kThreads / R2;
+  int64_t total_e = int64_t(1) << (n + t - pb);
+  int64_t grid = (total_e + E - 1) / E;
+  hipLaunchKernelGGL((k_qft_pass<T, R1, R2>), dim3(unsigned(grid)), dim3(kThreads), 0, s, static_cast<T*>(b0),
+                     static_cast<const T*>(b1), gather ? 1 : 0, n, t, pb, bb, hi, lo, h);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
+                    const double2* lo, int h, hipStream_t s) {
+  switch (pb) {
+    case 1: return go<T, 2, 1>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 2: return go<T, 4, 1>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 3: return go<T, 8, 1>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 4: return go<T, 16, 1>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 5: return go<T, 16, 2>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 6: return go<T, 16, 4>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 7: return go<T, 16, 8>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 8: return go<T, 16, 16>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+DftPlan make_dft_plan(int n) {
+  DftPlan p{};
+  p.npass = (n + 7) / 8;
+  int base = n / p.npass, extra = n % p.npass;
+  for (int q = 0; q < p.npass; ++q) p.bits[q] = base + (q < extra ? 1 : 0);
+  return p;
+}
+
+hipError_t launch_qft_pass(bool mixed, void* buf0, const void* buf1, bool gather, int n, int t, int pass_bits,
+                           int bits_before, const double2* tw_hi, const double2* tw_lo, int h, hipStream_t s) {
+  return mixed ? dispatch<float2>(buf0, buf1, gather, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, s)
+               : dispatch<double2>(buf0, buf1, gather, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, s);
+}
+
+}  // namespace qpe

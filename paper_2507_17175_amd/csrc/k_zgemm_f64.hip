@@ -1,0 +1,279 @@
+// Complex FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// Serves the power chain V_{k+1} = V_k V_k, the Newton-Schulz products
+// V^H V and V - V E / 2, and the FP64-form controlled step (rows of the state
+// whose control bit is set, times V^T). A complex product is carried as four
+// real MFMA products on separate real/imaginary accumulators:
+//   re += a.re b.re + (-a.im) b.im,   im += a.re b.im + a.im b.re.
+//
+// Tiling: 256 threads = 4 wave64s in a WM x WN grid; the workgroup tile is
+// BM x BN complex outputs, the K loop steps by BK = 16 complex. Operands are
+// staged in LDS as [k][i] / [k][j] (i or j contiguous, one double2 of
+// padding per row), and the next K slab is prefetched into registers while
+// the current one feeds the MFMAs. The 1-D grid is remapped so that each of
+// the 8 XCDs (which own separate L2 caches) walks a contiguous range of
+// tiles, keeping the tiles of one row block on one XCD.
+#include "qpe_internal.hpp"
+
+namespace qpe {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kBK = 16;
+
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+struct GatherArgs {
+  double2* buf0;
+  double2* buf1;
+  int k;
+  uint64_t pmask;
+};
+
+__device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
+  const int total = tiles_m * tiles_n;
+  int w = blockIdx.x;
+  if ((total & 7) == 0) w = (w & 7) * (total >> 3) + (w >> 3);
+  return make_int2(w / tiles_n, w % tiles_n);
+}
+
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
+  constexpr int FM = TM / 16, FN = TN / 16;  // 16x16 MFMA blocks per wave
+  constexpr int LA = BM * kBK / kThreads;    // A elements per thread per slab
+  constexpr int LB = BN * kBK / kThreads;
+  constexpr int PA = BM + 1, PB = BN + 1;    // padded LDS row length
+
+  __shared__ double2 As[kBK * PA];
+  __shared__ double2 Bs[kBK * PB];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  const int i0 = tile.x * BM, j0 = tile.y * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+
+  // Per-thread A row pointers (gather mode: rows of the state).
+  double2 ra[LA], rb[LB];
+
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      int idx = tid + q * kThreads;
+      int r, kk;
+      if (OPA == OP_N) {
+        r = idx / kBK;
+        kk = idx % kBK;
+      } else {
+        kk = idx / BM;
+        r = idx % BM;
+      }
+      int gi = i0 + r, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gi < a.M && gk < a.K) {
+        if (GATHER) {
+          int64_t j = ctrl_row(gi, g.k);
+          const double2* src = row_parity(j, g.pmask) ? g.buf1 : g.buf0;
+          v = src[j * a.lda + gk];
+        } else if (OPA == OP_N) {
+          v = a.A[int64_t(gi) * a.lda + gk];
+        } else {
+          v = a.A[int64_t(gk) * a.lda + gi];
+          if (OPA == OP_C) v.y = -v.y;
+        }
+      }
+      ra[q] = v;
+    }
+  };
+  auto store_a = [&]() {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      int idx = tid + q * kThreads;
+      int r, kk;
+      if (OPA == OP_N) {
+        r = idx / kBK;
+        kk = idx % kBK;
+      } else {
+        kk = idx / BM;
+        r = idx % BM;
+      }
+      As[kk * PA + r] = ra[q];
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      int idx = tid + q * kThreads;
+      int c, kk;
+      if (OPB == OP_N) {
+        kk = idx / BN;
+        c = idx % BN;
+      } else {
+        c = idx / kBK;
+        kk = idx % kBK;
+      }
+      int gj = j0 + c, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gj < a.N && gk < a.K) {
+        if (OPB == OP_N) {
+          v = a.B[int64_t(gk) * a.ldb + gj];
+        } else {
+          v = a.B[int64_t(gj) * a.ldb + gk];
+          if (OPB == OP_C) v.y = -v.y;
+        }
+      }
+      rb[q] = v;
+    }
+  };
+  auto store_b = [&]() {
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      int idx = tid + q * kThreads;
+      int c, kk;
+      if (OPB == OP_N) {
+        kk = idx / BN;
+        c = idx % BN;
+      } else {
+        c = idx / kBK;
+        kk = idx % kBK;
+      }
+      Bs[kk * PB + c] = rb[q];
+    }
+  };
+
+  f64x4 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+      acc_re[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc_im[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  const int nk = (a.K + kBK - 1) / kBK;
+  load_a(0);
+  load_b(0);
+  store_a();
+  store_b();
+  __syncthreads();
+
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) {
+      load_a((kt + 1) * kBK);
+      load_b((kt + 1) * kBK);
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < kBK / 4; ++k4) {
+      const int kr = k4 * 4 + lk;
+      double2 av[FM], bv[FN];
+#pragma unroll
+      for (int x = 0; x < FM; ++x) av[x] = As[kr * PA + wi0 + x * 16 + lr];
+#pragma unroll
+      for (int y = 0; y < FN; ++y) bv[y] = Bs[kr * PB + wj0 + y * 16 + lr];
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) {
+          acc_re[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].x, bv[y].x, acc_re[x][y], 0, 0, 0);
+          acc_im[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].x, bv[y].y, acc_im[x][y], 0, 0, 0);
+        }
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) {
+          acc_re[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[x].y, bv[y].y, acc_re[x][y], 0, 0, 0);
+          acc_im[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].y, bv[y].x, acc_im[x][y], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      store_a();
+      store_b();
+      __syncthreads();
+    }
+  }
+
+  // Epilogue. Output layout of the 16x16 f64 MFMA: lane l, element v holds
+  // row 4 * v + l / 16, column l % 16 of the block.
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi = i0 + wi0 + x * 16 + 4 * v + lk;
+        int gj = j0 + wj0 + y * 16 + lr;
+        if (gi >= a.M || gj >= a.N) continue;
+        double re = acc_re[x][y][v], im = acc_im[x][y][v];
+        if (GATHER) {
+          int64_t j = ctrl_row(gi, g.k);
+          double2* dst = row_parity(j, g.pmask) ? g.buf0 : g.buf1;
+          dst[j * a.ldc + gj] = make_double2(re, im);
+        } else {
+          double2 o;
+          o.x = a.alpha.x * re - a.alpha.y * im;
+          o.y = a.alpha.x * im + a.alpha.y * re;
+          if (a.beta.x != 0.0 || a.beta.y != 0.0) {
+            double2 c = a.Cin[int64_t(gi) * a.ldcin + gj];
+            o.x += a.beta.x * c.x - a.beta.y * c.y;
+            o.y += a.beta.x * c.y + a.beta.y * c.x;
+          }
+          a.C[int64_t(gi) * a.ldc + gj] = o;
+        }
+      }
+}
+
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+hipError_t go(const ZgemmArgs& a, const GatherArgs& g, hipStream_t s) {
+  int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(kThreads), 0, s, a, g);
+  return hipGetLastError();
+}
+
+template <int OPA, int OPB>
+hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s) {
+  GatherArgs g{};
+  // Small problems: 32x32 tiles keep more of the chip busy.
+  int64_t tiles64 = int64_t((a.M + 63) / 64) * ((a.N + 63) / 64);
+  if (tiles64 < 256) return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);
+  return go<OPA, OPB, false, 64, 64, 2, 2>(a, g, s);
+}
+
+}  // namespace
+
+hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s) {
+  switch (opA * 3 + opB) {
+    case 0: return dispatch_size<OP_N, OP_N>(a, s);
+    case 1: return dispatch_size<OP_N, OP_T>(a, s);
+    case 2: return dispatch_size<OP_N, OP_C>(a, s);
+    case 3: return dispatch_size<OP_T, OP_N>(a, s);
+    case 4: return dispatch_size<OP_T, OP_T>(a, s);
+    case 5: return dispatch_size<OP_T, OP_C>(a, s);
+    case 6: return dispatch_size<OP_C, OP_N>(a, s);
+    case 7: return dispatch_size<OP_C, OP_T>(a, s);
+    case 8: return dispatch_size<OP_C, OP_C>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n, int t, int k, uint64_t pmask,
+                           hipStream_t s) {
+  const int d = 1 << t;
+  ZgemmArgs a{};
+  a.M = 1 << (n - 1);
+  a.N = d;
+  a.K = d;
+  a.lda = d;
+  a.B = V;
+  a.ldb = d;
+  a.ldc = d;
+  GatherArgs g{buf0, buf1, k, pmask};
+  if (a.M >= 64 && d >= 64) return go<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, s);
+  return go<OP_N, OP_T, true, 32, 32, 2, 2>(a, g, s);
+}
+
+}  // namespace qpe

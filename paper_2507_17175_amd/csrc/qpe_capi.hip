@@ -1,0 +1,568 @@
+// C ABI of the QPE emulator: argument checks, workspace layout and the order
+// in which the stage kernels are enqueued (paper section 2, Fig. 1).
+//
+// Path for one instance (n measurement qubits, d = 2^t):
+//   H layer        every state row <- psi * 2^(-n/2)
+//   for k < n:     V_k = (V_{k-1})^2 in FP64, Newton-Schulz re-unitarised;
+//                  rows with bit k set <- row V_k^T (FP64 MFMA, split-BF16
+//                  MFMA, or VALU for d <= 16); state ping-pongs between two
+//                  buffers so the controlled GEMM never needs a copy-back
+//   inverse QFT    radix-2^b passes along the row axis
+//   readout        P(m) = sum_r |A[m, r]|^2 in FP64, digit order undone
+// Nothing here allocates device memory: all scratch lives in the caller's
+// workspace, so a run can be captured into a HIP graph.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qpe.h"
+#include "qpe_internal.hpp"
+
+#define QPE_API extern "C" __attribute__((visibility("default")))
+
+struct qpe_timer_pair {
+  hipEvent_t start, stop;
+  int which;
+};
+
+struct qpe_ctx {
+  int device;
+  hipStream_t stream;
+  std::string last_error;
+  // optional per-kernel timing
+  std::vector<qpe_timer_pair> timers;
+  size_t timers_used = 0;
+  bool timing = false;
+};
+
+namespace {
+
+using namespace qpe;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+int tw_split(int n) { return (n + 1) / 2; }
+
+// Workspace regions of one run (byte offsets; 0-size regions are unused).
+struct RunLayout {
+  size_t state0, state1, vbuf, tbuf, gbuf, planes, tw_hi, tw_lo, scratch, total;
+};
+
+RunLayout run_layout(int n, int t, int form, unsigned flags) {
+  RunLayout L{};
+  const size_t d = size_t(1) << t, N = size_t(1) << n;
+  const size_t amp = form == QPE_FORM_MIXED ? 8 : 16;
+  const size_t mat = d * d * 16;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.state0 = take(N * d * amp);
+  L.state1 = take(N * d * amp);
+  L.vbuf = take(mat);
+  L.tbuf = take(mat);
+  L.gbuf = (flags & QPE_NO_POLAR) ? 0 : take(mat);
+  L.planes = (form == QPE_FORM_MIXED && t >= 5) ? take(6 * d * d * 2) : 0;
+  const int h = tw_split(n);
+  L.tw_hi = take((N >> h) * 16);
+  L.tw_lo = take((size_t(1) << h) * 16);
+  L.scratch = take(64);
+  L.total = off;
+  return L;
+}
+
+qpe_status check_sizes(int n, int t) {
+  if (n < 1 || n > QPE_MAX_N_MEAS || t < 0 || t > QPE_MAX_N_MAT || n + t > QPE_MAX_TOTAL_QUBITS)
+    return QPE_ERR_SIZE;
+  return QPE_OK;
+}
+
+qpe_status check_problem(const qpe_problem& p, bool need_ptrs) {
+  qpe_status s = check_sizes(p.n_meas, p.n_mat);
+  if (s != QPE_OK) return s;
+  if (!need_ptrs) return QPE_OK;
+  if (!p.U || !p.psi || !p.prob) return QPE_ERR_ARG;
+  if (misaligned(p.U, 16) || misaligned(p.psi, 16) || misaligned(p.prob, 8)) return QPE_ERR_ALIGN;
+  return QPE_OK;
+}
+
+qpe_status check_form_flags(int form, unsigned flags) {
+  if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR)) return QPE_ERR_ARG;
+  return QPE_OK;
+}
+
+qpe_status check_workspace(const void* ws, size_t have, size_t need) {
+  if (need == 0) return QPE_OK;
+  if (!ws) return QPE_ERR_WORKSPACE;
+  if (misaligned(ws, kAlign)) return QPE_ERR_WORKSPACE;
+  if (have < need) return QPE_ERR_WORKSPACE;
+  return QPE_OK;
+}
+
+// Makes ctx->device current for the duration of a call and restores the
+// caller's device afterwards.
+struct DeviceGuard {
+  int old = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) return;
+    if (old != dev && hipSetDevice(dev) != hipSuccess) return;
+    ok = true;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+  }
+};
+
+qpe_status hip_fail(qpe_ctx* ctx, hipError_t e, const char* what) {
+  ctx->last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return QPE_ERR_HIP;
+}
+
+// Brackets the launches made inside its scope with a pair of events on the
+// context stream when timing is enabled and the pool has room.
+struct TimerScope {
+  qpe_ctx* ctx;
+  long idx = -1;
+  TimerScope(qpe_ctx* c, int which) : ctx(c) {
+    if (c->timing && c->timers_used < c->timers.size()) {
+      idx = long(c->timers_used++);
+      c->timers[idx].which = which;
+      (void)hipEventRecord(c->timers[idx].start, c->stream);
+    }
+  }
+  ~TimerScope() {
+    if (idx >= 0) (void)hipEventRecord(ctx->timers[idx].stop, ctx->stream);
+  }
+};
+
+#define QPE_HIP(ctx, expr)                               \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+// V_next = cur^2, then (unless no_polar) one Newton-Schulz step
+//   X <- X (3I - X^H X) / 2 = X - X (X^H X - I) / 2,
+// whose E = X^H X - I also yields the unitarity defect max|E_ij|.
+// sq and out are distinct from cur; out may equal the dead predecessor.
+qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
+                            bool polar, unsigned long long* defect) {
+  hipStream_t s = ctx->stream;
+  ZgemmArgs a{};
+  a.M = a.N = a.K = d;
+  a.A = cur;
+  a.lda = d;
+  a.B = cur;
+  a.ldb = d;
+  a.alpha = make_double2(1.0, 0.0);
+  a.beta = make_double2(0.0, 0.0);
+  a.C = sq;
+  a.ldc = d;
+  QPE_HIP(ctx, launch_zgemm(0, 0, a, s));
+  if (!polar) return QPE_OK;
+  ZgemmArgs h = a;
+  h.A = sq;
+  h.B = sq;
+  h.C = g;
+  QPE_HIP(ctx, launch_zgemm(2, 0, h, s));  // G = X^H X
+  QPE_HIP(ctx, launch_sub_identity_defect(g, d, defect, s));
+  ZgemmArgs c = a;
+  c.A = sq;
+  c.B = g;
+  c.alpha = make_double2(-0.5, 0.0);
+  c.beta = make_double2(1.0, 0.0);
+  c.Cin = sq;
+  c.ldcin = d;
+  c.C = out;
+  QPE_HIP(ctx, launch_zgemm(0, 0, c, s));  // X - X E / 2
+  return QPE_OK;
+}
+
+qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const double2* V, void* s0, void* s1,
+                      uint16_t* planes, uint64_t pmask) {
+  hipStream_t s = ctx->stream;
+  if (t <= 4) {
+    TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
+    QPE_HIP(ctx, launch_ctrl_small(mixed, s0, s1, V, n, t, k, pmask, s));
+  } else if (mixed) {
+    {
+      TimerScope ts(ctx, QPE_TIMER_SPLIT);
+      QPE_HIP(ctx, launch_split_pieces(V, planes, t, s));
+    }
+    TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
+    QPE_HIP(ctx, launch_ctrl_mixed(static_cast<float2*>(s0), static_cast<float2*>(s1), planes, n, t, k, pmask, s));
+  } else {
+    TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
+    QPE_HIP(ctx, launch_ctrl_f64(static_cast<double2*>(s0), static_cast<double2*>(s1), V, n, t, k, pmask, s));
+  }
+  return QPE_OK;
+}
+
+qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, const void* s1, bool gather,
+                          double* prob, double2* tw_hi, double2* tw_lo) {
+  hipStream_t s = ctx->stream;
+  const int h = tw_split(n);
+  QPE_HIP(ctx, launch_twiddles(tw_hi, tw_lo, n, h, s));
+  DftPlan plan = make_dft_plan(n);
+  int before = 0;
+  for (int q = 0; q < plan.npass; ++q) {
+    TimerScope ts(ctx, QPE_TIMER_QFT);
+    QPE_HIP(ctx, launch_qft_pass(mixed, s0, s1, gather && q == 0, n, t, plan.bits[q], before, tw_hi, tw_lo, h, s));
+    before += plan.bits[q];
+  }
+  TimerScope ts(ctx, QPE_TIMER_PROB);
+  QPE_HIP(ctx, launch_prob(mixed, s0, prob, n, t, plan, s));
+  return QPE_OK;
+}
+
+qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags, char* ws, qpe_report* report) {
+  const int n = p.n_meas, t = p.n_mat, d = 1 << t;
+  const bool mixed = form == QPE_FORM_MIXED;
+  const bool polar = !(flags & QPE_NO_POLAR);
+  const RunLayout L = run_layout(n, t, form, flags);
+  hipStream_t s = ctx->stream;
+  void* s0 = ws + L.state0;
+  void* s1 = ws + L.state1;
+  double2* A = reinterpret_cast<double2*>(ws + L.vbuf);
+  double2* B = reinterpret_cast<double2*>(ws + L.tbuf);
+  double2* G = polar ? reinterpret_cast<double2*>(ws + L.gbuf) : nullptr;
+  uint16_t* planes = (mixed && t >= 5) ? reinterpret_cast<uint16_t*>(ws + L.planes) : nullptr;
+  unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + L.scratch);
+  const double2* psi = static_cast<const double2*>(p.psi);
+
+  QPE_HIP(ctx, launch_zero_u64(defect, 1, s));
+  {
+    TimerScope ts(ctx, QPE_TIMER_HLAYER);
+    QPE_HIP(ctx, launch_h_broadcast(mixed, psi, s0, n, t, s));
+  }
+  const double2* cur = static_cast<const double2*>(p.U);
+  for (int k = 0; k < n; ++k) {
+    if (k > 0) {
+      double2* sq = (cur == A) ? B : A;
+      double2* other = (sq == A) ? B : A;
+      TimerScope ts(ctx, QPE_TIMER_POWERS);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect);
+      if (st != QPE_OK) return st;
+      cur = polar ? other : sq;
+    }
+    qpe_status st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1);
+    if (st != QPE_OK) return st;
+  }
+  qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, true, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
+                                 reinterpret_cast<double2*>(ws + L.tw_lo));
+  if (st != QPE_OK) return st;
+  if (report) QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, s));
+  return QPE_OK;
+}
+
+const char* const kStatusText[] = {
+    "QPE_OK",
+    "QPE_ERR_ARG: null pointer, unknown form or flag, or bad count",
+    "QPE_ERR_SIZE: n_meas or n_mat out of range",
+    "QPE_ERR_ALIGN: a device pointer is misaligned",
+    "QPE_ERR_WORKSPACE: workspace missing, misaligned or too small",
+    "QPE_ERR_OOM: host allocation failed",
+    "QPE_ERR_NO_DEVICE: no usable HIP device",
+    "QPE_ERR_HIP: a HIP call or kernel launch failed",
+    "QPE_ERR_UNSUPPORTED: not implemented in this build",
+};
+
+}  // namespace
+
+QPE_API const char* qpe_status_string(int status) {
+  if (status < 0 || status > QPE_ERR_UNSUPPORTED) return "unknown qpe_status";
+  return kStatusText[status];
+}
+
+QPE_API const char* qpe_version(void) { return "0.1.0"; }
+
+QPE_API const char* qpe_last_error(const qpe_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
+  if (!out) return QPE_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return QPE_ERR_NO_DEVICE;
+  if (device < 0 || device >= count) return QPE_ERR_NO_DEVICE;
+  qpe_ctx* c = new (std::nothrow) qpe_ctx;
+  if (!c) return QPE_ERR_OOM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  *out = c;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_set_stream(qpe_ctx* ctx, void* stream) {
+  if (!ctx) return QPE_ERR_ARG;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return QPE_OK;
+}
+
+static void free_timers(qpe_ctx* ctx) {
+  for (auto& p : ctx->timers) {
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
+  }
+  ctx->timers.clear();
+  ctx->timers_used = 0;
+  ctx->timing = false;
+}
+
+QPE_API qpe_status qpe_ctx_destroy(qpe_ctx* ctx) {
+  if (ctx) free_timers(ctx);
+  delete ctx;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_enable_timing(qpe_ctx* ctx, int max_pairs) {
+  if (!ctx || max_pairs < 1 || max_pairs > (1 << 20)) return QPE_ERR_ARG;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  free_timers(ctx);
+  ctx->timers.reserve(size_t(max_pairs));
+  for (int i = 0; i < max_pairs; ++i) {
+    qpe_timer_pair p{};
+    hipError_t e = hipEventCreate(&p.start);
+    if (e == hipSuccess) e = hipEventCreate(&p.stop);
+    if (e != hipSuccess) {
+      free_timers(ctx);
+      return hip_fail(ctx, e, "hipEventCreate");
+    }
+    p.which = -1;
+    ctx->timers.push_back(p);
+  }
+  ctx->timing = true;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_reset_timing(qpe_ctx* ctx) {
+  if (!ctx) return QPE_ERR_ARG;
+  ctx->timers_used = 0;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_read_timing(qpe_ctx* ctx, int timer, int* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms || timer < 0 || timer >= QPE_TIMER_COUNT) return QPE_ERR_ARG;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  int cnt = 0;
+  double sum = 0.0;
+  for (size_t i = 0; i < ctx->timers_used; ++i) {
+    const qpe_timer_pair& p = ctx->timers[i];
+    if (p.which != timer) continue;
+    QPE_HIP(ctx, hipEventSynchronize(p.stop));
+    float ms = 0.f;
+    QPE_HIP(ctx, hipEventElapsedTime(&ms, p.start, p.stop));
+    ++cnt;
+    sum += ms;
+  }
+  *launches = cnt;
+  *total_ms = sum;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_workspace_size(const qpe_problem* problems, int count, int form, unsigned flags,
+                                      size_t* bytes) {
+  if (!problems || !bytes || count < 1) return QPE_ERR_ARG;
+  qpe_status s = check_form_flags(form, flags);
+  if (s != QPE_OK) return s;
+  size_t need = 0;
+  for (int i = 0; i < count; ++i) {
+    s = check_problem(problems[i], false);
+    if (s != QPE_OK) return s;
+    size_t b = run_layout(problems[i].n_meas, problems[i].n_mat, form, flags).total;
+    if (b > need) need = b;
+  }
+  *bytes = need;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int form, unsigned flags,
+                                 const void* workspace, size_t workspace_bytes, const void* report) {
+  if (!problems || count < 1) return QPE_ERR_ARG;
+  qpe_status s = check_form_flags(form, flags);
+  if (s != QPE_OK) return s;
+  size_t need = 0;
+  for (int i = 0; i < count; ++i) {
+    s = check_problem(problems[i], true);
+    if (s != QPE_OK) return s;
+    size_t b = run_layout(problems[i].n_meas, problems[i].n_mat, form, flags).total;
+    if (b > need) need = b;
+  }
+  if (report && misaligned(report, 8)) return QPE_ERR_ALIGN;
+  return check_workspace(workspace, workspace_bytes, need);
+}
+
+QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
+                           void* workspace, size_t workspace_bytes, qpe_report* report) {
+  if (!ctx) return QPE_ERR_ARG;
+  qpe_status s = qpe_check_run(problems, count, form, flags, workspace, workspace_bytes, report);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  // Instances run one after another on the context stream, sharing the
+  // workspace (stream order separates them).
+  for (int i = 0; i < count; ++i) {
+    s = run_one(ctx, problems[i], form, flags, static_cast<char*>(workspace), report ? report + i : nullptr);
+    if (s != QPE_OK) return s;
+  }
+  return QPE_OK;
+}
+
+// ------------------------------------------------------------ stage entries
+
+QPE_API qpe_status qpe_powers_workspace_size(int n_mat, size_t* bytes) {
+  if (!bytes) return QPE_ERR_ARG;
+  if (n_mat < 0 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
+  size_t mat = (size_t(1) << (2 * n_mat)) * 16;
+  *bytes = 2 * align_up(mat) + align_up(64);
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_k, unsigned flags, void* V_out,
+                              void* workspace, size_t workspace_bytes, qpe_report* report) {
+  if (!ctx || !U || !V_out) return QPE_ERR_ARG;
+  if (n_mat < 0 || n_mat > QPE_MAX_N_MAT || count_k < 1 || count_k > QPE_MAX_N_MEAS) return QPE_ERR_SIZE;
+  if (flags & ~unsigned(QPE_NO_POLAR)) return QPE_ERR_ARG;
+  if (misaligned(U, 16) || misaligned(V_out, 16) || (report && misaligned(report, 8))) return QPE_ERR_ALIGN;
+  size_t need = 0;
+  qpe_powers_workspace_size(n_mat, &need);
+  qpe_status s = check_workspace(workspace, workspace_bytes, need);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  const int d = 1 << n_mat;
+  const size_t mat = size_t(d) * d;
+  char* ws = static_cast<char*>(workspace);
+  double2* sq = reinterpret_cast<double2*>(ws);
+  double2* g = reinterpret_cast<double2*>(ws + align_up(mat * 16));
+  unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + 2 * align_up(mat * 16));
+  double2* V = static_cast<double2*>(V_out);
+  const bool polar = !(flags & QPE_NO_POLAR);
+  QPE_HIP(ctx, launch_zero_u64(defect, 1, ctx->stream));
+  QPE_HIP(ctx, hipMemcpyAsync(V, U, mat * 16, hipMemcpyDeviceToDevice, ctx->stream));
+  for (int k = 1; k < count_k; ++k) {
+    const double2* cur = V + (k - 1) * mat;
+    double2* out = V + k * mat;
+    s = square_and_polar(ctx, d, cur, polar ? sq : out, g, out, polar, defect);
+    if (s != QPE_OK) return s;
+  }
+  if (report) {
+    // Only the defect is meaningful here; copy it into the first field.
+    QPE_HIP(ctx, hipMemcpyAsync(report, defect, sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_controlled_step_workspace_size(int n_meas, int n_mat, int form, size_t* bytes) {
+  if (!bytes) return QPE_ERR_ARG;
+  qpe_status s = check_sizes(n_meas, n_mat);
+  if (s != QPE_OK) return s;
+  if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
+  const size_t d = size_t(1) << n_mat, N = size_t(1) << n_meas;
+  size_t amp = form == QPE_FORM_MIXED ? 8 : 16;
+  *bytes = align_up(N * d * amp) + ((form == QPE_FORM_MIXED && n_mat >= 5) ? align_up(6 * d * d * 2) : 0);
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_controlled_step(qpe_ctx* ctx, int n_meas, int n_mat, int form, int k, const void* V,
+                                       void* state, void* workspace, size_t workspace_bytes) {
+  if (!ctx || !V || !state) return QPE_ERR_ARG;
+  size_t need = 0;
+  qpe_status s = qpe_controlled_step_workspace_size(n_meas, n_mat, form, &need);
+  if (s != QPE_OK) return s;
+  if (k < 0 || k >= n_meas) return QPE_ERR_SIZE;
+  if (misaligned(V, 16) || misaligned(state, 16)) return QPE_ERR_ALIGN;
+  s = check_workspace(workspace, workspace_bytes, need);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  const bool mixed = form == QPE_FORM_MIXED;
+  const size_t d = size_t(1) << n_mat, N = size_t(1) << n_meas;
+  char* ws = static_cast<char*>(workspace);
+  void* other = ws;
+  uint16_t* planes = reinterpret_cast<uint16_t*>(ws + align_up(N * d * (mixed ? 8 : 16)));
+  // pmask 0: every row is read from `state`; updated rows land in `other`.
+  s = controlled(ctx, mixed, n_meas, n_mat, k, static_cast<const double2*>(V), state, other, planes, 0);
+  if (s != QPE_OK) return s;
+  QPE_HIP(ctx, launch_copy_rows_back(mixed, state, other, n_meas, n_mat, k, ctx->stream));
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size_t* bytes) {
+  if (!bytes) return QPE_ERR_ARG;
+  qpe_status s = check_sizes(n_meas, n_mat);
+  if (s != QPE_OK) return s;
+  if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
+  const int h = tw_split(n_meas);
+  *bytes = align_up((size_t(1) << (n_meas - h)) * 16) + align_up((size_t(1) << h) * 16);
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_iqft_probs(qpe_ctx* ctx, int n_meas, int n_mat, int form, void* state, double* prob,
+                                  void* workspace, size_t workspace_bytes) {
+  if (!ctx || !state || !prob) return QPE_ERR_ARG;
+  size_t need = 0;
+  qpe_status s = qpe_iqft_workspace_size(n_meas, n_mat, form, &need);
+  if (s != QPE_OK) return s;
+  if (misaligned(state, 16) || misaligned(prob, 8)) return QPE_ERR_ALIGN;
+  s = check_workspace(workspace, workspace_bytes, need);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  const int h = tw_split(n_meas);
+  char* ws = static_cast<char*>(workspace);
+  double2* tw_hi = reinterpret_cast<double2*>(ws);
+  double2* tw_lo = reinterpret_cast<double2*>(ws + align_up((size_t(1) << (n_meas - h)) * 16));
+  return iqft_and_probs(ctx, form == QPE_FORM_MIXED, n_meas, n_mat, state, nullptr, false, prob, tw_hi, tw_lo);
+}
+
+QPE_API qpe_status qpe_zgemm(qpe_ctx* ctx, char opA, char opB, int M, int N, int K, const double* alpha,
+                             const void* A, int lda, const void* B, int ldb, const double* beta, const void* Cin,
+                             int ldcin, void* C, int ldc) {
+  if (!ctx || !alpha || !beta || !A || !B || !C) return QPE_ERR_ARG;
+  auto op_code = [](char o) { return o == 'N' ? 0 : o == 'T' ? 1 : o == 'C' ? 2 : -1; };
+  int oa = op_code(opA), ob = op_code(opB);
+  if (oa < 0 || ob < 0) return QPE_ERR_ARG;
+  if (M < 1 || N < 1 || K < 1 || M > 65536 || N > 65536 || K > 65536) return QPE_ERR_SIZE;
+  const bool use_cin = beta[0] != 0.0 || beta[1] != 0.0;
+  if (use_cin && !Cin) return QPE_ERR_ARG;
+  // leading dimensions must cover a row of the stored (not op'ed) matrix
+  if (lda < (oa == 0 ? K : M) || ldb < (ob == 0 ? N : K) || ldc < N || (use_cin && ldcin < N)) return QPE_ERR_SIZE;
+  if (misaligned(A, 16) || misaligned(B, 16) || misaligned(C, 16) || (use_cin && misaligned(Cin, 16)))
+    return QPE_ERR_ALIGN;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  ZgemmArgs a{};
+  a.M = M;
+  a.N = N;
+  a.K = K;
+  a.A = static_cast<const double2*>(A);
+  a.lda = lda;
+  a.B = static_cast<const double2*>(B);
+  a.ldb = ldb;
+  a.alpha = make_double2(alpha[0], alpha[1]);
+  a.beta = make_double2(beta[0], beta[1]);
+  a.Cin = static_cast<const double2*>(Cin);
+  a.ldcin = ldcin;
+  a.C = static_cast<double2*>(C);
+  a.ldc = ldc;
+  QPE_HIP(ctx, launch_zgemm(oa, ob, a, ctx->stream));
+  return QPE_OK;
+}

@@ -1,0 +1,142 @@
+"""The C ABI on the host: the library loads, exports every declared symbol,
+and its argument checks return the documented status codes without a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.libutil import ensure_built
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    from paper_2507_17175_amd import qpe
+    return qpe.load_library()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "qpe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qpe_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2507_17175_amd import qpe
+    assert sorted(qpe.EXPORTS) == names
+
+
+def test_status_strings(L):
+    assert L.qpe_status_string(0) == b"QPE_OK"
+    for s in range(1, 9):
+        assert L.qpe_status_string(s).startswith(b"QPE_ERR_")
+    assert b"unknown" in L.qpe_status_string(99)
+    assert L.qpe_version() == b"0.1.0"
+
+
+def _problems(shapes, ptr=0x10000):
+    from paper_2507_17175_amd.qpe import Problem
+    arr = (Problem * len(shapes))()
+    for i, (n, t) in enumerate(shapes):
+        arr[i].n_meas, arr[i].n_mat = n, t
+        arr[i].U = arr[i].psi = arr[i].prob = ptr
+    return arr
+
+
+def test_workspace_size(L):
+    out = ctypes.c_size_t()
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 0, ctypes.byref(out)) == 0
+    small = out.value
+    assert small >= 2 * 256 * 4 * 8
+    assert L.qpe_workspace_size(_problems([(16, 10)]), 1, 1, 0, ctypes.byref(out)) == 0
+    # two c64 state buffers of 2^26 amplitudes dominate
+    assert out.value >= 2 * (1 << 26) * 8
+    mixed = out.value
+    assert L.qpe_workspace_size(_problems([(16, 10)]), 1, 0, 0, ctypes.byref(out)) == 0
+    assert out.value > mixed  # complex128 state
+    # batch: the largest instance
+    assert L.qpe_workspace_size(_problems([(8, 2), (16, 10)]), 2, 1, 0, ctypes.byref(out)) == 0
+    assert out.value == mixed
+
+
+@pytest.mark.parametrize("n,t,code", [(0, 2, 2), (31, 2, 2), (8, -1, 2), (8, 16, 2), (30, 10, 2), (20, 14, 0)])
+def test_size_limits(L, n, t, code):
+    out = ctypes.c_size_t()
+    assert L.qpe_workspace_size(_problems([(n, t)]), 1, 1, 0, ctypes.byref(out)) == code
+
+
+def test_bad_form_flags_count(L):
+    out = ctypes.c_size_t()
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 2, 0, ctypes.byref(out)) == 1
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 4, ctypes.byref(out)) == 1
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 0, 1, 0, ctypes.byref(out)) == 1
+    assert L.qpe_workspace_size(None, 1, 1, 0, ctypes.byref(out)) == 1
+
+
+def test_check_run(L):
+    out = ctypes.c_size_t()
+    p = _problems([(8, 2)])
+    assert L.qpe_workspace_size(p, 1, 1, 0, ctypes.byref(out)) == 0
+    need = out.value
+    ws = 0x100000  # 256-aligned fake device address: never dereferenced
+    assert L.qpe_check_run(p, 1, 1, 0, ws, need, None) == 0
+    assert L.qpe_check_run(p, 1, 1, 0, ws, need - 1, None) == 4
+    assert L.qpe_check_run(p, 1, 1, 0, ws + 16, need, None) == 4
+    assert L.qpe_check_run(p, 1, 1, 0, None, need, None) == 4
+    assert L.qpe_check_run(p, 1, 1, 0, ws, need, ws + 4) == 3
+    bad = _problems([(8, 2)])
+    bad[0].U = 0x10008
+    assert L.qpe_check_run(bad, 1, 1, 0, ws, need, None) == 3
+    bad[0].U = 0x10000
+    bad[0].prob = 0x10004
+    assert L.qpe_check_run(bad, 1, 1, 0, ws, need, None) == 3
+    bad[0].prob = None
+    assert L.qpe_check_run(bad, 1, 1, 0, ws, need, None) == 1
+    assert L.qpe_check_run(p, 1, 7, 0, ws, need, None) == 1
+
+
+def test_null_context(L):
+    p = _problems([(8, 2)])
+    assert L.qpe_run(None, p, 1, 1, 0, 0x100000, 1 << 30, None) == 1
+    al = (ctypes.c_double * 2)(1.0, 0.0)
+    assert L.qpe_zgemm(None, b"N", b"N", 4, 4, 4, al, 0x1000, 4, 0x1000, 4, al, 0x1000, 4, 0x1000, 4) == 1
+    assert L.qpe_powers(None, 2, 0x1000, 3, 0, 0x1000, 0x100000, 1 << 20, None) == 1
+    assert L.qpe_ctx_destroy(None) == 0
+    assert L.qpe_last_error(None) == b""
+
+
+def test_stage_workspace_sizes(L):
+    out = ctypes.c_size_t()
+    assert L.qpe_powers_workspace_size(10, ctypes.byref(out)) == 0
+    assert out.value >= 2 * 1024 * 1024 * 16
+    assert L.qpe_powers_workspace_size(16, ctypes.byref(out)) == 2
+    assert L.qpe_controlled_step_workspace_size(12, 6, 1, ctypes.byref(out)) == 0
+    assert out.value >= (1 << 18) * 8
+    assert L.qpe_iqft_workspace_size(20, 8, 1, ctypes.byref(out)) == 0
+    assert L.qpe_iqft_workspace_size(0, 8, 1, ctypes.byref(out)) == 2
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be present")
+def test_no_device(L):
+    h = ctypes.c_void_p()
+    assert L.qpe_ctx_create(ctypes.byref(h), 0, None) == 6
+    assert L.qpe_ctx_create(None, 0, None) == 1
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path):
+    from paper_2507_17175_amd import qpe
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        qpe._lib_saved = qpe._lib
+        try:
+            qpe._lib = None
+            qpe.load_library(str(tmp_path / "missing.so"))
+        finally:
+            qpe._lib = qpe._lib_saved
