@@ -34,6 +34,31 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the controlled-product kernel at the c2 workload,
+# from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
+# factors a plain 1 GiB copy gives), keyed by the first 16 hex digits of the
+# SHA-256 of the kernel source the counters were taken on. A changed kernel
+# reports traffic null until it is measured again.
+TRAFFIC = {
+    "28059941e64d89af": {"fetch_bytes": 525566.5 * 2 * 1024, "write_bytes": 262144.0 * 1024,
+                         "profile": "profiles/ctrl_bf16x6_qpe_n16_t10_hbm.md"},
+}
+CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
+
+
+def traffic_for_current_kernel():
+    import hashlib
+    try:
+        h = hashlib.sha256(open(CTRL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    rec = TRAFFIC.get(h)
+    if rec is None:
+        return None
+    return {"bytes_per_launch": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
+            "write_bytes": rec["write_bytes"], "source": rec["profile"]}
+
+
 CONFIGS = {
     "c1": "qpe-n8-t2 (Haar 4x4, exact-bit eigenphase k/256, eigenvector input)",
     "c2": "qpe-n16-t10 (Haar 1024x1024, uniform eigenphase, eigenvector input)",
@@ -50,7 +75,23 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (calibrates the HBM byte "
+                         "counters of a profiler pass) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib: int) -> int:
+    """A plain copy kernel of known size: reads and writes mib MiB, 3 times."""
+    import torch
+    n = mib * (1 << 20)
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": n, "launches": 3}), flush=True)
+    return 0
 
 
 def time_form(qpe, torch, prob, form, steps, warmup):
@@ -78,6 +119,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         return 2
+    if a.copy_probe_mib:
+        return copy_probe(a.copy_probe_mib)
     import torch
     from paper_2507_17175_amd import qpe
     from workloads import config_problems
@@ -103,7 +146,7 @@ def main():
         "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
         "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
         "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt,
-        "traffic": None,
+        "traffic": traffic_for_current_kernel() if (a.config == "c2" and t >= 5) else None,
     }
     breakdown = {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing.items()}
 
