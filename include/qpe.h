@@ -205,6 +205,22 @@ qpe_status qpe_ctx_enable_timing(qpe_ctx *ctx, int max_pairs);
 qpe_status qpe_ctx_reset_timing(qpe_ctx *ctx);
 qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *total_ms);
 
+/* ---- kernel variants (tile shapes), chosen by an offline autotuner ----
+ * Each kernel class has variants 1..count (different tile shapes and
+ * pipelining); 0 selects the built-in default. A context applies its
+ * choice to every later call. All variants compute the same result up to
+ * rounding order. */
+enum {
+  QPE_KERNEL_CTRL_MIXED = 0, /* split-BF16 controlled GEMM (d >= 32)  */
+  QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain          */
+  QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
+  QPE_KERNEL_COUNT = 3
+};
+qpe_status qpe_kernel_variants(int kernel_class, int *count);
+/* n_mat selects the operator size the choice applies to (0..QPE_MAX_N_MAT),
+ * or -1 for every size. */
+qpe_status qpe_ctx_set_variant(qpe_ctx *ctx, int kernel_class, int n_mat, int variant);
+
 /* ---- misc ---- */
 
 /* Static text for a status code (never NULL). */

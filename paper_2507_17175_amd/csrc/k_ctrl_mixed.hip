@@ -12,24 +12,32 @@
 // v_mfma_f32_32x32x16_bf16. The complex product uses four real products:
 //   re += a.re w.re + a.im (-w.im),   im += a.re w.im + a.im w.re.
 //
-// Tiling: 4 wave64s, workgroup tile BM rows x BN complex columns, K slab of
-// 32 complex. The FP32 A slab is split into 6 BF16 planes (3 pieces x re/im)
-// as it is written to LDS; the B slab arrives pre-split and pre-blocked from
-// HBM. LDS rows are padded to 80 bytes so that the 16-byte fragment reads of
-// 32 consecutive rows hit distinct banks. The state ping-pongs between two
-// buffers (read buf[parity], write the other), so there is no copy-back and
-// no read-after-write hazard between workgroups that share rows.
+// The state ping-pongs between two buffers (read buf[parity], write the
+// other), so there is no copy-back and no read-after-write hazard between
+// workgroups that share rows. The operator arrives pre-split as six BF16
+// planes (hi/mid/lo x re/im), blocked by 16 columns so that the K slab of a
+// column tile is one contiguous run.
+//
+// Two kernels:
+//  * k_ctrl_bf16x6_db (default): 8 wave64s (two per SIMD, so one wave's LDS
+//    waits are covered by the other's matrix-core work), K slab of 16
+//    complex, double-buffered LDS: the split-and-store of slab s+1 and the
+//    global loads of slab s+2 overlap the MFMAs of slab s, one barrier per
+//    slab. LDS rows are padded to 48 bytes: the 16-byte fragment reads of 16
+//    consecutive rows then cover all 64 banks once.
+//  * k_ctrl_bf16x6 (variant 1): 4 wave64s, K slab of 32 complex, single
+//    LDS buffer with register prefetch.
 #include "qpe_internal.hpp"
 
 namespace qpe {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kBK = 32;   // complex K per slab (= blocking of the operator planes)
-constexpr int kRow = 40;  // padded LDS row, in bf16 elements (80 bytes)
+constexpr int kPlaneBlock = 16;  // column blocking of the operator planes
 
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
 __device__ inline void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
   h = (__bf16)x;
@@ -52,19 +60,72 @@ __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
   return make_int2(w / tiles_n, w % tiles_n);
 }
 
+// Six MFMA products of one (row block, column block) pair for one K chunk of
+// 16: piece pairs with index sum <= 2, four real products per complex one.
+template <int FM, int FN>
+__device__ __forceinline__ void mma_bf16x6(f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
+                                           const bf16x8 (&av)[FM][6], const bf16x8 (&bv)[FN][6],
+                                           const bf16x8 (&bneg)[FN][3]) {
+  constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
+  constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int pa = PA[c], pb = PB[c];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int y = 0; y < FN; ++y) {
+        acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb], acc_re[x][y], 0, 0, 0);
+        acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb + 1], acc_im[x][y], 0, 0, 0);
+      }
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int y = 0; y < FN; ++y) {
+        acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bneg[y][pb], acc_re[x][y], 0, 0, 0);
+        acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bv[y][2 * pb], acc_im[x][y], 0, 0, 0);
+      }
+  }
+}
+
+// Output layout of the 32x32 MFMA: lane l, element v holds row
+// 8 * (v / 4) + 4 * (l / 32) + v % 4, column l % 32 of the block.
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const f32x16 (&acc_im)[FM][FN],
+                                           float2* buf0, float2* buf1, int M, int d, int k, uint64_t pmask, int row0,
+                                           int col0, int lane) {
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      int gi = row0 + 32 * x + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if (gi >= M) continue;
+      int64_t j = ctrl_row(gi, k);
+      float2* dst = (row_parity(j, pmask) ? buf0 : buf1) + j * d + col0 + (lane & 31);
+#pragma unroll
+      for (int y = 0; y < FN; ++y) dst[32 * y] = make_float2(acc_re[x][y][v], acc_im[x][y][v]);
+    }
+}
+
+// ----------------------------------------------------------------- variant 2
 template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
-              int k, uint64_t pmask) {
-  static_assert(WM * WN == 4, "4 waves");
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask) {
+  constexpr int NT = 512;
+  static_assert(WM * WN == 8, "8 waves");
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
-  constexpr int CA = BM * 4 / kThreads;        // 8-complex A chunks per thread
-  constexpr int CB = 6 * BN * 4 / kThreads;    // 16-byte B chunks per thread
-  static_assert(CA >= 1 && CB >= 1, "tile too small");
+  constexpr int KS = 16;       // complex K per slab
+  constexpr int ROW = 24;      // padded LDS row in bf16 (48 bytes)
+  constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
+  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int CA = BM * KS / 4 / NT;  // 4-complex A chunks per thread
+  constexpr int NB = 12 * BN;              // 16-byte B chunks per slab
+  constexpr int CB = (NB + NT - 1) / NT;   // per thread (the last one guarded)
+  static_assert(CA >= 1 && CA * NT * 4 == BM * KS, "tile/thread mismatch");
 
-  __shared__ __attribute__((aligned(16))) uint16_t As[6 * BM * kRow];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[6 * BN * kRow];
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];
 
   const int d = 1 << t;
   const int64_t dd = int64_t(d) * d;
@@ -75,71 +136,70 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
   const int i0 = tile.x * BM, j0 = tile.y * BN;
   const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
 
-  // Source row pointers of this thread's A chunks.
+  // Rows past M (only when M < BM) read row M-1 instead: the loads stay
+  // unconditional (a guarded load becomes a branch that makes the compiler
+  // wait for all outstanding loads), and the epilogue drops those rows.
   const float2* src_row[CA];
-  bool row_ok[CA];
 #pragma unroll
   for (int q = 0; q < CA; ++q) {
-    int c = tid + q * kThreads;
-    int gi = i0 + c / 4;
-    row_ok[q] = gi < M;
-    int64_t j = ctrl_row(row_ok[q] ? gi : 0, k);
-    src_row[q] = (row_parity(j, pmask) ? buf1 : buf0) + j * d;
+    int c = tid + q * NT;
+    int gi = min(i0 + c / 4, M - 1);
+    int64_t j = ctrl_row(gi, k);
+    src_row[q] = (row_parity(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
   }
 
-  float4 ra[CA][4];
+  float4 ra[CA][2];
   u32x4 rb[CB];
 
-  auto load_global = [&](int kt) {
-    const int k0 = kt * kBK;
+  auto load_global = [&](int s) {
+    const int k0 = s * KS;
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
-      int c = tid + q * kThreads;
-      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0 + 8 * (c & 3));
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ra[q][u] = row_ok[q] ? p[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[q][0] = p[0];
+      ra[q][1] = p[1];
     }
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
-      int idx = tid + q * kThreads;
-      int pl = idx / (BN * 4), w = idx % (BN * 4);
-      const u32x4* p = reinterpret_cast<const u32x4*>(planes + pl * dd + (int64_t(kt) * d + j0) * kBK) + w;
-      rb[q] = *p;
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      rb[q] = *reinterpret_cast<const u32x4*>(planes + pl * dd + (int64_t(s) * d + j0 + (w >> 1)) * kPlaneBlock +
+                                              8 * (w & 1));
     }
   };
 
-  auto store_lds = [&]() {
+  auto store_lds = [&](int b) {
+    uint16_t* base = lds + b * BUF;
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
-      int c = tid + q * kThreads;
-      int r = c / 4, kc = c & 3;
-      bf16x8 pc[6];
+      int c = tid + q * NT;
+      int r = c / 4, kq = c & 3;
+      float v[8] = {ra[q][0].x, ra[q][0].y, ra[q][0].z, ra[q][0].w,
+                    ra[q][1].x, ra[q][1].y, ra[q][1].z, ra[q][1].w};
+      bf16x4 pc[6];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        float v[4] = {ra[q][u].x, ra[q][u].y, ra[q][u].z, ra[q][u].w};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          __bf16 a, b, cc;
-          split3(v[2 * h], a, b, cc);       // real part
-          pc[0][2 * u + h] = a;
-          pc[2][2 * u + h] = b;
-          pc[4][2 * u + h] = cc;
-          split3(v[2 * h + 1], a, b, cc);   // imaginary part
-          pc[1][2 * u + h] = a;
-          pc[3][2 * u + h] = b;
-          pc[5][2 * u + h] = cc;
-        }
+        __bf16 h, m, l;
+        split3(v[2 * u], h, m, l);  // real part
+        pc[0][u] = h;
+        pc[2][u] = m;
+        pc[4][u] = l;
+        split3(v[2 * u + 1], h, m, l);  // imaginary part
+        pc[1][u] = h;
+        pc[3][u] = m;
+        pc[5][u] = l;
       }
 #pragma unroll
       for (int pl = 0; pl < 6; ++pl)
-        *reinterpret_cast<bf16x8*>(&As[(pl * BM + r) * kRow + 8 * kc]) = pc[pl];
+        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[pl];
     }
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
-      int idx = tid + q * kThreads;
-      int pl = idx / (BN * 4), w = idx % (BN * 4);
-      int col = w / 4, kc = w & 3;
-      *reinterpret_cast<u32x4*>(&Bs[(pl * BN + col) * kRow + 8 * kc]) = rb[q];
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      *reinterpret_cast<u32x4*>(base + 6 * A_PLANE + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
     }
   };
 
@@ -154,7 +214,144 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
         acc_im[x][y][v] = 0.f;
       }
 
-  const int nk = d / kBK;
+  const int nk = d / KS;
+  const int lr = lane & 31, ko = (lane >> 5) * 8;
+  load_global(0);
+  store_lds(0);
+  if (nk > 1) load_global(1);
+  __syncthreads();
+
+  for (int s = 0; s < nk; ++s) {
+    const uint16_t* base = lds + (s & 1) * BUF;
+    bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bv[y][pl] =
+            *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+#pragma unroll
+      for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
+    }
+    mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+    if (s + 1 < nk) store_lds((s + 1) & 1);
+    if (s + 2 < nk) load_global(s + 2);
+    __syncthreads();
+  }
+
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+}
+
+// ----------------------------------------------------------------- variant 1
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
+              int k, uint64_t pmask) {
+  constexpr int NT = 256;
+  constexpr int KS = 32;   // complex K per slab (two operator-plane blocks)
+  constexpr int ROW = 40;  // padded LDS row in bf16 (80 bytes)
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int CA = BM * 4 / NT;      // 8-complex A chunks per thread
+  constexpr int CB = 6 * BN * 4 / NT;  // 16-byte B chunks per thread
+  static_assert(CA >= 1 && CB >= 1, "tile too small");
+
+  __shared__ __attribute__((aligned(16))) uint16_t As[6 * BM * ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[6 * BN * ROW];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  const int i0 = tile.x * BM, j0 = tile.y * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+
+  // Rows past M read row M-1 (unconditional loads; see variant 2).
+  const float2* src_row[CA];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int c = tid + q * NT;
+    int gi = min(i0 + c / 4, M - 1);
+    int64_t j = ctrl_row(gi, k);
+    src_row[q] = (row_parity(j, pmask) ? buf1 : buf0) + j * d;
+  }
+
+  float4 ra[CA][4];
+  u32x4 rb[CB];
+
+  auto load_global = [&](int kt) {
+    const int k0 = kt * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tid + q * NT;
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0 + 8 * (c & 3));
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ra[q][u] = p[u];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      int pl = idx / (BN * 4), w = idx % (BN * 4);
+      int col = w / 4, kc = w & 3;
+      int64_t blk = 2 * int64_t(kt) + (kc >> 1);
+      rb[q] = *reinterpret_cast<const u32x4*>(planes + pl * dd + (blk * d + j0 + col) * kPlaneBlock + 8 * (kc & 1));
+    }
+  };
+
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tid + q * NT;
+      int r = c / 4, kc = c & 3;
+      bf16x8 pc[6];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float v[4] = {ra[q][u].x, ra[q][u].y, ra[q][u].z, ra[q][u].w};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          __bf16 a, b, cc;
+          split3(v[2 * h], a, b, cc);
+          pc[0][2 * u + h] = a;
+          pc[2][2 * u + h] = b;
+          pc[4][2 * u + h] = cc;
+          split3(v[2 * h + 1], a, b, cc);
+          pc[1][2 * u + h] = a;
+          pc[3][2 * u + h] = b;
+          pc[5][2 * u + h] = cc;
+        }
+      }
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x8*>(&As[(pl * BM + r) * ROW + 8 * kc]) = pc[pl];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      int pl = idx / (BN * 4), w = idx % (BN * 4);
+      int col = w / 4, kc = w & 3;
+      *reinterpret_cast<u32x4*>(&Bs[(pl * BN + col) * ROW + 8 * kc]) = rb[q];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[x][y][v] = 0.f;
+        acc_im[x][y][v] = 0.f;
+      }
+
+  const int nk = d / KS;
   load_global(0);
   store_lds();
   __syncthreads();
@@ -165,42 +362,21 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const int ko = kk * 16 + lk;
-      bf16x8 av[FM][6];
-      bf16x8 bv[FN][6], bneg[FN][3];
+      bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
         for (int pl = 0; pl < 6; ++pl)
-          av[x][pl] = *reinterpret_cast<const bf16x8*>(&As[(pl * BM + wi0 + 32 * x + lr) * kRow + ko]);
+          av[x][pl] = *reinterpret_cast<const bf16x8*>(&As[(pl * BM + wi0 + 32 * x + lr) * ROW + ko]);
 #pragma unroll
       for (int y = 0; y < FN; ++y) {
 #pragma unroll
         for (int pl = 0; pl < 6; ++pl)
-          bv[y][pl] = *reinterpret_cast<const bf16x8*>(&Bs[(pl * BN + wj0 + 32 * y + lr) * kRow + ko]);
+          bv[y][pl] = *reinterpret_cast<const bf16x8*>(&Bs[(pl * BN + wj0 + 32 * y + lr) * ROW + ko]);
 #pragma unroll
         for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
       }
-      // piece pairs (A piece, B piece) with index sum <= 2
-      constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
-      constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const int pa = PA[c], pb = PB[c];
-#pragma unroll
-        for (int x = 0; x < FM; ++x)
-#pragma unroll
-          for (int y = 0; y < FN; ++y) {
-            acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb], acc_re[x][y], 0, 0, 0);
-            acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb + 1], acc_im[x][y], 0, 0, 0);
-          }
-#pragma unroll
-        for (int x = 0; x < FM; ++x)
-#pragma unroll
-          for (int y = 0; y < FN; ++y) {
-            acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bneg[y][pb], acc_re[x][y], 0, 0, 0);
-            acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bv[y][2 * pb], acc_im[x][y], 0, 0, 0);
-          }
-      }
+      mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -209,38 +385,33 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
     }
   }
 
-  // Epilogue. Output layout of the 32x32 MFMA: lane l, element v holds row
-  // 8 * (v / 4) + 4 * (l / 32) + v % 4, column l % 32 of the block.
-#pragma unroll
-  for (int x = 0; x < FM; ++x)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      int gi = i0 + wi0 + 32 * x + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      if (gi >= M) continue;
-      int64_t j = ctrl_row(gi, k);
-      float2* dst = (row_parity(j, pmask) ? buf0 : buf1) + j * d + j0 + wj0 + lr;
-#pragma unroll
-      for (int y = 0; y < FN; ++y) dst[32 * y] = make_float2(acc_re[x][y][v], acc_im[x][y][v]);
-    }
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
-template <int BM, int BN, int WM, int WN>
-hipError_t go(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
-              hipStream_t s) {
+template <int NT, typename K>
+hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
+                  uint64_t pmask, hipStream_t s) {
   int M = 1 << (n - 1);
   int tiles = ((M + BM - 1) / BM) * ((1 << t) / BN);
-  hipLaunchKernelGGL((k_ctrl_bf16x6<BM, BN, WM, WN>), dim3(tiles), dim3(kThreads), 0, s, buf0, buf1, planes, n, t, k,
-                     pmask);
+  hipLaunchKernelGGL(kernel, dim3(tiles), dim3(NT), 0, s, buf0, buf1, planes, n, t, k, pmask);
   return hipGetLastError();
 }
 
 }  // namespace
 
+int ctrl_mixed_variants() { return 2; }
+
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
-                             hipStream_t s) {
-  if (t >= 7) return go<128, 128, 2, 2>(buf0, buf1, planes, n, t, k, pmask, s);
-  if (t == 6) return go<128, 64, 2, 2>(buf0, buf1, planes, n, t, k, pmask, s);
-  if (t == 5) return go<128, 32, 4, 1>(buf0, buf1, planes, n, t, k, pmask, s);
+                             hipStream_t s, int variant) {
+  if (variant == 1) {
+    if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (t >= 7) return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+  if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+  if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
   return hipErrorInvalidValue;
 }
 

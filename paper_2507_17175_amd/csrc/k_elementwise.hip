@@ -81,8 +81,8 @@ __device__ inline uint16_t bf16_rne(double x, double* rounded) {
 // matrix V (d x d) is split, per real component w, into three BF16 pieces
 // w = hi + mid + lo (each the RNE rounding of the remaining residual). Plane
 // p = 2 * piece + component (component 0 = real, 1 = imaginary). Inside a
-// plane the layout is blocked by 32 columns: element (row j, col c) sits at
-// ((c / 32) * d + j) * 32 + c % 32, so that a tile of consecutive rows and 32
+// plane the layout is blocked by 16 columns: element (row j, col c) sits at
+// ((c / 16) * d + j) * 16 + c % 16, so that a tile of consecutive rows and 16
 // consecutive columns is contiguous.
 __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
                                                            int t) {
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __rest
   for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
     int64_t j = e >> t, c = e & (d - 1);
     double2 v = V[e];
-    int64_t dst = (((c >> 5) * d + j) << 5) + (c & 31);
+    int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
     double w[2] = {v.x, v.y};
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {

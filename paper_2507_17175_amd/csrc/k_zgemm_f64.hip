@@ -19,7 +19,6 @@ namespace qpe {
 
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kBK = 16;
 
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
@@ -31,6 +30,15 @@ struct GatherArgs {
   uint64_t pmask;
 };
 
+// buf0 or buf1 by arithmetic on the addresses: a plain select between two
+// fields of the by-value argument struct compiles into a per-lane load of
+// the pointer from the argument segment, then a wait, then the data load.
+__device__ inline double2* pick(const GatherArgs& g, int which) {
+  uintptr_t b0 = reinterpret_cast<uintptr_t>(g.buf0);
+  uintptr_t delta = reinterpret_cast<uintptr_t>(g.buf1) - b0;
+  return reinterpret_cast<double2*>(b0 + (which ? delta : uintptr_t(0)));
+}
+
 __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
   const int total = tiles_m * tiles_n;
   int w = blockIdx.x;
@@ -39,12 +47,14 @@ __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
 }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
-  static_assert(WM * WN == 4, "4 waves");
+__global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
+  constexpr int kThreads = 64 * WM * WN;
+  static_assert(WM * WN == 4 || WM * WN == 8, "4 or 8 waves");
   constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
   constexpr int FM = TM / 16, FN = TN / 16;  // 16x16 MFMA blocks per wave
   constexpr int LA = BM * kBK / kThreads;    // A elements per thread per slab
   constexpr int LB = BN * kBK / kThreads;
+  static_assert(LA * kThreads == BM * kBK && LB * kThreads == BN * kBK, "tile/thread mismatch");
   constexpr int PA = BM + 1, PB = BN + 1;    // padded LDS row length
 
   __shared__ double2 As[kBK * PA];
@@ -72,20 +82,23 @@ __global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
         r = idx % BM;
       }
       int gi = i0 + r, gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (gi < a.M && gk < a.K) {
-        if (GATHER) {
-          int64_t j = ctrl_row(gi, g.k);
-          const double2* src = row_parity(j, g.pmask) ? g.buf1 : g.buf0;
-          v = src[j * a.lda + gk];
-        } else if (OPA == OP_N) {
-          v = a.A[int64_t(gi) * a.lda + gk];
-        } else {
-          v = a.A[int64_t(gk) * a.lda + gi];
-          if (OPA == OP_C) v.y = -v.y;
-        }
+      // Out-of-range elements load a clamped in-range address and are
+      // zeroed by a select: the load itself stays unconditional (a guarded
+      // load becomes a branch after which the compiler waits for every
+      // outstanding load).
+      const bool ok = gi < a.M && gk < a.K;
+      const int ci = min(gi, a.M - 1), ck = min(gk, a.K - 1);
+      double2 v;
+      if (GATHER) {
+        int64_t j = ctrl_row(ci, g.k);
+        v = pick(g, row_parity(j, g.pmask))[j * a.lda + ck];
+      } else if (OPA == OP_N) {
+        v = a.A[int64_t(ci) * a.lda + ck];
+      } else {
+        v = a.A[int64_t(ck) * a.lda + ci];
+        if (OPA == OP_C) v.y = -v.y;
       }
-      ra[q] = v;
+      ra[q] = ok ? v : make_double2(0.0, 0.0);
     }
   };
   auto store_a = [&]() {
@@ -116,16 +129,16 @@ __global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
         kk = idx % kBK;
       }
       int gj = j0 + c, gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (gj < a.N && gk < a.K) {
-        if (OPB == OP_N) {
-          v = a.B[int64_t(gk) * a.ldb + gj];
-        } else {
-          v = a.B[int64_t(gj) * a.ldb + gk];
-          if (OPB == OP_C) v.y = -v.y;
-        }
+      const bool ok = gj < a.N && gk < a.K;
+      const int cj = min(gj, a.N - 1), ck = min(gk, a.K - 1);
+      double2 v;
+      if (OPB == OP_N) {
+        v = a.B[int64_t(ck) * a.ldb + cj];
+      } else {
+        v = a.B[int64_t(cj) * a.ldb + ck];
+        if (OPB == OP_C) v.y = -v.y;
       }
-      rb[q] = v;
+      rb[q] = ok ? v : make_double2(0.0, 0.0);
     }
   };
   auto store_b = [&]() {
@@ -211,7 +224,7 @@ __global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
         double re = acc_re[x][y][v], im = acc_im[x][y][v];
         if (GATHER) {
           int64_t j = ctrl_row(gi, g.k);
-          double2* dst = row_parity(j, g.pmask) ? g.buf0 : g.buf1;
+          double2* dst = pick(g, 1 - row_parity(j, g.pmask));
           dst[j * a.ldc + gj] = make_double2(re, im);
         } else {
           double2 o;
@@ -230,38 +243,57 @@ __global__ void __launch_bounds__(kThreads) k_zgemm(ZgemmArgs a, GatherArgs g) {
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 hipError_t go(const ZgemmArgs& a, const GatherArgs& g, hipStream_t s) {
   int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(kThreads), 0, s, a, g);
+  hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
   return hipGetLastError();
 }
 
+// Tile variants of the power-chain GEMM: (BM, BN, waves).
+//   1: 32x32, 4 waves   2: 64x64, 4 waves   3: 64x64, 8 waves
+//   4: 128x64, 8 waves  5: 64x32, 4 waves
 template <int OPA, int OPB>
-hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s) {
+hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
   GatherArgs g{};
-  // Small problems: 32x32 tiles keep more of the chip busy.
-  int64_t tiles64 = int64_t((a.M + 63) / 64) * ((a.N + 63) / 64);
-  if (tiles64 < 256) return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);
-  return go<OPA, OPB, false, 64, 64, 2, 2>(a, g, s);
-}
-
-}  // namespace
-
-hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s) {
-  switch (opA * 3 + opB) {
-    case 0: return dispatch_size<OP_N, OP_N>(a, s);
-    case 1: return dispatch_size<OP_N, OP_T>(a, s);
-    case 2: return dispatch_size<OP_N, OP_C>(a, s);
-    case 3: return dispatch_size<OP_T, OP_N>(a, s);
-    case 4: return dispatch_size<OP_T, OP_T>(a, s);
-    case 5: return dispatch_size<OP_T, OP_C>(a, s);
-    case 6: return dispatch_size<OP_C, OP_N>(a, s);
-    case 7: return dispatch_size<OP_C, OP_T>(a, s);
-    case 8: return dispatch_size<OP_C, OP_C>(a, s);
+  if (variant == 0) {
+    // Default (measured on MI355X): 64x64 tiles with 8 waves once there
+    // are >= 128 of them (d >= 1024: 7.2 ms per 15 squaring steps vs 7.9 ms
+    // for 32x32), 32x32 tiles below (d = 256: 1.34 ms vs 2.5 ms).
+    int64_t tiles64 = int64_t((a.M + 63) / 64) * ((a.N + 63) / 64);
+    variant = tiles64 >= 128 ? 3 : 1;
+  }
+  switch (variant) {
+    case 1: return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);
+    case 2: return go<OPA, OPB, false, 64, 64, 2, 2>(a, g, s);
+    case 3: return go<OPA, OPB, false, 64, 64, 4, 2>(a, g, s);
+    case 4: return go<OPA, OPB, false, 128, 64, 4, 2>(a, g, s);
+    case 5: return go<OPA, OPB, false, 64, 32, 2, 2>(a, g, s);
   }
   return hipErrorInvalidValue;
 }
 
+}  // namespace
+
+int zgemm_variants() { return 5; }
+int ctrl_f64_variants() { return 3; }
+
+hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant) {
+  switch (opA * 3 + opB) {
+    case 0: return dispatch_size<OP_N, OP_N>(a, s, variant);
+    case 1: return dispatch_size<OP_N, OP_T>(a, s, variant);
+    case 2: return dispatch_size<OP_N, OP_C>(a, s, variant);
+    case 3: return dispatch_size<OP_T, OP_N>(a, s, variant);
+    case 4: return dispatch_size<OP_T, OP_T>(a, s, variant);
+    case 5: return dispatch_size<OP_T, OP_C>(a, s, variant);
+    case 6: return dispatch_size<OP_C, OP_N>(a, s, variant);
+    case 7: return dispatch_size<OP_C, OP_T>(a, s, variant);
+    case 8: return dispatch_size<OP_C, OP_C>(a, s, variant);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Controlled step variants: 1: 64x64, 4 waves; 2: 128x64, 8 waves;
+// 3: 128x128, 8 waves. Small sizes fall back to 32x32 tiles.
 hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n, int t, int k, uint64_t pmask,
-                           hipStream_t s) {
+                           hipStream_t s, int variant) {
   const int d = 1 << t;
   ZgemmArgs a{};
   a.M = 1 << (n - 1);
@@ -272,8 +304,15 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
   a.ldb = d;
   a.ldc = d;
   GatherArgs g{buf0, buf1, k, pmask};
-  if (a.M >= 64 && d >= 64) return go<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, s);
-  return go<OP_N, OP_T, true, 32, 32, 2, 2>(a, g, s);
+  if (a.M < 128 || d < 64) return go<OP_N, OP_T, true, 32, 32, 2, 2>(a, g, s);
+  if (variant == 0) variant = 1;
+  if (variant == 3 && d < 128) variant = 2;
+  switch (variant) {
+    case 1: return go<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, s);
+    case 2: return go<OP_N, OP_T, true, 128, 64, 4, 2>(a, g, s);
+    case 3: return go<OP_N, OP_T, true, 128, 128, 2, 4>(a, g, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace qpe

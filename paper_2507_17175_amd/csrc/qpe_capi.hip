@@ -35,6 +35,8 @@ struct qpe_ctx {
   std::vector<qpe_timer_pair> timers;
   size_t timers_used = 0;
   bool timing = false;
+  // kernel variant per class (0 = default)
+  int variant[QPE_KERNEL_COUNT][QPE_MAX_N_MAT + 1] = {};
 };
 
 namespace {
@@ -159,6 +161,7 @@ struct TimerScope {
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
                             bool polar, unsigned long long* defect) {
   hipStream_t s = ctx->stream;
+  const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
   a.M = a.N = a.K = d;
   a.A = cur;
@@ -169,13 +172,13 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   a.beta = make_double2(0.0, 0.0);
   a.C = sq;
   a.ldc = d;
-  QPE_HIP(ctx, launch_zgemm(0, 0, a, s));
+  QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));
   if (!polar) return QPE_OK;
   ZgemmArgs h = a;
   h.A = sq;
   h.B = sq;
   h.C = g;
-  QPE_HIP(ctx, launch_zgemm(2, 0, h, s));  // G = X^H X
+  QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // G = X^H X
   QPE_HIP(ctx, launch_sub_identity_defect(g, d, defect, s));
   ZgemmArgs c = a;
   c.A = sq;
@@ -185,7 +188,7 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   c.Cin = sq;
   c.ldcin = d;
   c.C = out;
-  QPE_HIP(ctx, launch_zgemm(0, 0, c, s));  // X - X E / 2
+  QPE_HIP(ctx, launch_zgemm(0, 0, c, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // X - X E / 2
   return QPE_OK;
 }
 
@@ -201,10 +204,12 @@ qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const doubl
       QPE_HIP(ctx, launch_split_pieces(V, planes, t, s));
     }
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
-    QPE_HIP(ctx, launch_ctrl_mixed(static_cast<float2*>(s0), static_cast<float2*>(s1), planes, n, t, k, pmask, s));
+    QPE_HIP(ctx, launch_ctrl_mixed(static_cast<float2*>(s0), static_cast<float2*>(s1), planes, n, t, k, pmask, s,
+                                    ctx->variant[QPE_KERNEL_CTRL_MIXED][t]));
   } else {
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
-    QPE_HIP(ctx, launch_ctrl_f64(static_cast<double2*>(s0), static_cast<double2*>(s1), V, n, t, k, pmask, s));
+    QPE_HIP(ctx, launch_ctrl_f64(static_cast<double2*>(s0), static_cast<double2*>(s1), V, n, t, k, pmask, s,
+                                 ctx->variant[QPE_KERNEL_CTRL_F64][t]));
   }
   return QPE_OK;
 }
@@ -300,6 +305,33 @@ QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   *out = c;
+  return QPE_OK;
+}
+
+static int variant_count(int kernel_class) {
+  switch (kernel_class) {
+    case QPE_KERNEL_CTRL_MIXED: return ctrl_mixed_variants();
+    case QPE_KERNEL_ZGEMM: return zgemm_variants();
+    case QPE_KERNEL_CTRL_F64: return ctrl_f64_variants();
+  }
+  return -1;
+}
+
+QPE_API qpe_status qpe_kernel_variants(int kernel_class, int* count) {
+  if (!count) return QPE_ERR_ARG;
+  int c = variant_count(kernel_class);
+  if (c < 0) return QPE_ERR_ARG;
+  *count = c;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_set_variant(qpe_ctx* ctx, int kernel_class, int n_mat, int variant) {
+  if (!ctx) return QPE_ERR_ARG;
+  int c = variant_count(kernel_class);
+  if (c < 0 || variant < 0 || variant > c) return QPE_ERR_ARG;
+  if (n_mat < -1 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
+  for (int t = 0; t <= QPE_MAX_N_MAT; ++t)
+    if (n_mat < 0 || t == n_mat) ctx->variant[kernel_class][t] = variant;
   return QPE_OK;
 }
 
@@ -563,6 +595,8 @@ QPE_API qpe_status qpe_zgemm(qpe_ctx* ctx, char opA, char opB, int M, int N, int
   a.ldcin = ldcin;
   a.C = static_cast<double2*>(C);
   a.ldc = ldc;
-  QPE_HIP(ctx, launch_zgemm(oa, ob, a, ctx->stream));
+  int tz = 31 - __builtin_clz(unsigned(N));  // size key: floor(log2 N), clamped
+  if (tz > QPE_MAX_N_MAT) tz = QPE_MAX_N_MAT;
+  QPE_HIP(ctx, launch_zgemm(oa, ob, a, ctx->stream, ctx->variant[QPE_KERNEL_ZGEMM][tz]));
   return QPE_OK;
 }

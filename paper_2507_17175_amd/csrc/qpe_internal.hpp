@@ -78,15 +78,19 @@ struct ZgemmArgs {
   double2* C;
   long ldc;
 };
-hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s);
+hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant);
+int zgemm_variants();
 
 // Controlled step k, FP64 form: rows j with bit k set, read from
 // buf[row_parity(j,k)], written to the other buffer: s <- V s.
 hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n, int t, int k,
-                           uint64_t pmask, hipStream_t s);
-// Controlled step k, mixed form (d >= 32): split-BF16 operator planes.
+                           uint64_t pmask, hipStream_t s, int variant);
+int ctrl_f64_variants();
+// Controlled step k, mixed form (d >= 32): split-BF16 operator planes
+// (blocked by 16 columns). variant 0 = default, 1..ctrl_mixed_variants().
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
-                             uint64_t pmask, hipStream_t s);
+                             uint64_t pmask, hipStream_t s, int variant);
+int ctrl_mixed_variants();
 // Controlled step k for d <= 16 on the vector ALUs (both forms).
 hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* V, int n, int t, int k,
                              uint64_t pmask, hipStream_t s);

@@ -38,7 +38,10 @@ EXPORTS = (
     "qpe_controlled_step", "qpe_iqft_workspace_size", "qpe_iqft_probs", "qpe_zgemm",
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
+    "qpe_kernel_variants", "qpe_ctx_set_variant",
 )
+
+KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2}
 
 TIMERS = {"ctrl_gemm": 0, "powers": 1, "split": 2, "qft": 3, "prob": 4, "hlayer": 5}
 
@@ -95,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_check_run": (st, [ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, vp, sz, vp]),
             "qpe_ctx_enable_timing": (st, [vp, i32]),
             "qpe_ctx_reset_timing": (st, [vp]),
+            "qpe_kernel_variants": (st, [i32, ctypes.POINTER(i32)]),
+            "qpe_ctx_set_variant": (st, [vp, i32, i32, i32]),
             "qpe_ctx_read_timing": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
             "qpe_status_string": (ctypes.c_char_p, [i32]),
             "qpe_last_error": (ctypes.c_char_p, [vp]),
@@ -131,6 +136,12 @@ class Context:
     def bind_current_stream(self) -> None:
         stream = torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().qpe_ctx_set_stream(self.handle, ctypes.c_void_p(stream)), "qpe_ctx_set_stream")
+
+    def set_variant(self, kernel_class: str, variant: int, n_mat: int = -1) -> None:
+        """Select tile variant `variant` (0 = default) of a kernel class for
+        operators of 2^n_mat (-1: all sizes)."""
+        _check(load_library().qpe_ctx_set_variant(self.handle, KERNEL_CLASSES[kernel_class], int(n_mat),
+                                                  int(variant)), "qpe_ctx_set_variant", self.handle)
 
     def enable_timing(self, max_pairs: int = 4096) -> None:
         _check(load_library().qpe_ctx_enable_timing(self.handle, int(max_pairs)), "qpe_ctx_enable_timing",
@@ -377,3 +388,10 @@ class Runner:
         if self.report_buf is None:
             return None
         return np.frombuffer(self.report_buf.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
+
+
+def kernel_variants(kernel_class: str) -> int:
+    """Number of tile variants of a kernel class (variant 0 = default)."""
+    c = ctypes.c_int()
+    _check(load_library().qpe_kernel_variants(KERNEL_CLASSES[kernel_class], ctypes.byref(c)), "qpe_kernel_variants")
+    return c.value
