@@ -109,9 +109,9 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const
 
 // ----------------------------------------------------------------- variant 2
 template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
-                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
-                                                         uint64_t pmask) {
+__device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                             const uint16_t* __restrict__ planes, int n, int t, int k,
+                                             uint64_t pmask, int tile_m, int tile_n) {
   constexpr int NT = 512;
   static_assert(WM * WN == 8, "8 waves");
   constexpr int TM = BM / WM, TN = BN / WN;
@@ -131,9 +131,7 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf
   const int64_t dd = int64_t(d) * d;
   const int M = 1 << (n - 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
-  const int2 tile = xcd_tile(tiles_m, tiles_n);
-  const int i0 = tile.x * BM, j0 = tile.y * BN;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
   const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
 
   // Rows past M (only when M < BM) read row M-1 instead: the loads stay
@@ -247,11 +245,20 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_db_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
 // ----------------------------------------------------------------- variant 1
 template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
-              int k, uint64_t pmask) {
+__device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                             const uint16_t* __restrict__ planes, int n, int t, int k,
+                                             uint64_t pmask, int tile_m, int tile_n) {
   constexpr int NT = 256;
   constexpr int KS = 32;   // complex K per slab (two operator-plane blocks)
   constexpr int ROW = 40;  // padded LDS row in bf16 (80 bytes)
@@ -269,9 +276,7 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
   const int64_t dd = int64_t(d) * d;
   const int M = 1 << (n - 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
-  const int2 tile = xcd_tile(tiles_m, tiles_n);
-  const int i0 = tile.x * BM, j0 = tile.y * BN;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
   const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
 
   // Rows past M read row M-1 (unconditional loads; see variant 2).
@@ -388,6 +393,39 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
+              int k, uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_v1_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+// Grouped controlled step k over the instances of a launch table; the tile
+// shape follows the operator size class of the launch (d = 32, 64, >= 128).
+template <int KIND>
+__global__ void __launch_bounds__(KIND == BK_CTRL_M32 ? 256 : 512)
+kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int polar) {
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const RunLayout L = run_layout(D.n, D.t, true, polar != 0);
+  float2* s0 = reinterpret_cast<float2*>(D.ws + L.state0);
+  float2* s1 = reinterpret_cast<float2*>(D.ws + L.state1);
+  const uint16_t* planes = reinterpret_cast<const uint16_t*>(D.ws + L.planes);
+  const uint64_t pmask = (uint64_t(1) << step) - 1;
+  constexpr int BN = KIND == BK_CTRL_M32 ? 32 : (KIND == BK_CTRL_M64 ? 64 : 128);
+  const int tiles_n = (1 << D.t) / BN;
+  const int tm = int(local / tiles_n), tn = int(local % tiles_n);
+  if constexpr (KIND == BK_CTRL_M32)
+    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+  else if constexpr (KIND == BK_CTRL_M64)
+    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+  else
+    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+}
+
 template <int NT, typename K>
 hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
                   uint64_t pmask, hipStream_t s) {
@@ -413,6 +451,25 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
   if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                                   bool polar, hipStream_t s) {
+  const int p = polar ? 1 : 0;
+  switch (kind) {
+    case BK_CTRL_M32:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M32>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, p);
+      break;
+    case BK_CTRL_M64:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M64>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
+      break;
+    case BK_CTRL_M128:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M128>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace qpe

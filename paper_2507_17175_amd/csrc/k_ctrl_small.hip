@@ -17,9 +17,11 @@ template <typename T> struct Real;
 template <> struct Real<float2> { typedef float type; };
 template <> struct Real<double2> { typedef double type; };
 
+// Rows i in [i0, i1) (stride) of the gathered set of step k.
 template <typename T, int D>
-__global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T* __restrict__ buf1,
-                                                         const double2* __restrict__ V, int n, int k, uint64_t pmask) {
+__device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restrict__ buf1,
+                                                const double2* __restrict__ V, int k, uint64_t pmask, int64_t i0,
+                                                int64_t i1, int64_t stride) {
   typedef typename Real<T>::type R;
   __shared__ R Vre[D * D], Vim[D * D];
   for (int e = threadIdx.x; e < D * D; e += kThreads) {
@@ -27,8 +29,7 @@ __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T
     Vim[e] = R(V[e].y);
   }
   __syncthreads();
-  const int64_t M = int64_t(1) << (n - 1);
-  for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < M; i += int64_t(gridDim.x) * kThreads) {
+  for (int64_t i = i0; i < i1; i += stride) {
     int64_t j = ctrl_row(i, k);
     int p = row_parity(j, pmask);
     const T* src = (p ? buf1 : buf0) + j * D;
@@ -62,6 +63,41 @@ __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T
 }
 
 template <typename T, int D>
+__global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T* __restrict__ buf1,
+                                                         const double2* __restrict__ V, int n, int k, uint64_t pmask) {
+  const int64_t M = int64_t(1) << (n - 1);
+  ctrl_small_rows<T, D>(buf0, buf1, V, k, pmask, blockIdx.x * int64_t(kThreads) + threadIdx.x, M,
+                        int64_t(gridDim.x) * kThreads);
+}
+
+// Grouped controlled step k over the d <= 16 instances of a launch table:
+// 256 gathered rows per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDesc* __restrict__ desc,
+                                                          const int32_t* __restrict__ table, int polar) {
+  constexpr bool mixed = sizeof(T) == 8;
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const bool pol = polar != 0;
+  const RunLayout L = run_layout(D.n, D.t, mixed, pol);
+  const int slot = power_slot(step, pol);
+  const double2* V = slot == 0 ? D.U : reinterpret_cast<const double2*>(D.ws + (slot == 1 ? L.vbuf : L.tbuf));
+  T* b0 = reinterpret_cast<T*>(D.ws + L.state0);
+  T* b1 = reinterpret_cast<T*>(D.ws + L.state1);
+  const uint64_t pmask = (uint64_t(1) << step) - 1;
+  const int64_t M = int64_t(1) << (D.n - 1);
+  const int64_t i0 = local * kThreads + threadIdx.x;
+  switch (D.t) {
+    case 0: ctrl_small_rows<T, 1>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+    case 1: ctrl_small_rows<T, 2>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+    case 2: ctrl_small_rows<T, 4>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+    case 3: ctrl_small_rows<T, 8>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+    case 4: ctrl_small_rows<T, 16>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+  }
+}
+
+template <typename T, int D>
 hipError_t go(void* b0, void* b1, const double2* V, int n, int k, uint64_t pmask, hipStream_t s) {
   int64_t M = int64_t(1) << (n - 1);
   int64_t g = (M + kThreads - 1) / kThreads;
@@ -89,6 +125,17 @@ hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* 
                              uint64_t pmask, hipStream_t s) {
   return mixed ? dispatch<float2>(buf0, buf1, V, n, t, k, pmask, s)
                : dispatch<double2>(buf0, buf1, V, n, t, k, pmask, s);
+}
+
+hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                   bool polar, hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_ctrl_small<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
+                       polar ? 1 : 0);
+  else
+    hipLaunchKernelGGL(kb_ctrl_small<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
+                       polar ? 1 : 0);
+  return hipGetLastError();
 }
 
 }  // namespace qpe

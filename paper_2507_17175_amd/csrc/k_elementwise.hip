@@ -1,6 +1,8 @@
 // Bandwidth-bound kernels of the QPE path: Hadamard layer, twiddle tables,
 // operator split into BF16 pieces, Newton-Schulz identity subtraction with
-// the unitarity defect, probability readout and the per-run report.
+// the unitarity defect, probability readout and the per-run report; their
+// grouped (batched) forms; and the device-side builders of the batch
+// descriptors and launch tables.
 #include "qpe_internal.hpp"
 
 #include <cmath>
@@ -18,24 +20,28 @@ inline int grid_for(int64_t work, int per_block = kThreads, int cap = 256 * 64) 
   return int(g);
 }
 
+__device__ inline double h_scale(int n) {
+  // 2^(-n/2): exact power of two times sqrt(1/2) for odd n
+  return ldexp(1.0, -(n / 2)) * ((n & 1) ? 0.70710678118654752440 : 1.0);
+}
+
+// ----------------------------------------------------------- device bodies
+
 // H on every qubit of |0...0> gives the uniform superposition, so every row
-// of the (N x d) state becomes psi * 2^(-n/2) (Fig. 1, H layer).
-__global__ void __launch_bounds__(kThreads) k_h_broadcast_c64(const double2* __restrict__ psi,
-                                                              float4* __restrict__ out, int64_t pairs,
-                                                              int dmask, double scale) {
-  for (int64_t q = blockIdx.x * int64_t(kThreads) + threadIdx.x; q < pairs;
-       q += int64_t(gridDim.x) * kThreads) {
+// of the (N x d) state becomes psi * 2^(-n/2) (Fig. 1, H layer). The complex64
+// form writes two amplitudes per float4 (pairs [p0, p1)).
+__device__ inline void h_range_c64(const double2* __restrict__ psi, float4* __restrict__ out, int64_t p0, int64_t p1,
+                                   int dmask, double scale, int64_t stride) {
+  for (int64_t q = p0; q < p1; q += stride) {
     double2 a = psi[(2 * q) & dmask];
     double2 b = psi[(2 * q + 1) & dmask];
     out[q] = make_float4(float(a.x * scale), float(a.y * scale), float(b.x * scale), float(b.y * scale));
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_h_broadcast_c128(const double2* __restrict__ psi,
-                                                               double2* __restrict__ out, int64_t total,
-                                                               int dmask, double scale) {
-  for (int64_t q = blockIdx.x * int64_t(kThreads) + threadIdx.x; q < total;
-       q += int64_t(gridDim.x) * kThreads) {
+__device__ inline void h_range_c128(const double2* __restrict__ psi, double2* __restrict__ out, int64_t e0, int64_t e1,
+                                    int dmask, double scale, int64_t stride) {
+  for (int64_t q = e0; q < e1; q += stride) {
     double2 a = psi[q & dmask];
     out[q] = make_double2(a.x * scale, a.y * scale);
   }
@@ -43,20 +49,17 @@ __global__ void __launch_bounds__(kThreads) k_h_broadcast_c128(const double2* __
 
 // tw_lo[t] = exp(-2 pi i t / N) for t < 2^h; tw_hi[u] = exp(-2 pi i u 2^h / N).
 // The angle -2 t / N (in units of pi) is exact in binary.
-__global__ void __launch_bounds__(kThreads) k_twiddles(double2* __restrict__ tw_hi, double2* __restrict__ tw_lo,
-                                                       int n, int h) {
-  int64_t nlo = int64_t(1) << h, nhi = int64_t(1) << (n - h);
-  for (int64_t t = blockIdx.x * int64_t(kThreads) + threadIdx.x; t < nlo + nhi;
-       t += int64_t(gridDim.x) * kThreads) {
-    int64_t e = t < nlo ? t : ((t - nlo) << h);
-    double x = -std::ldexp(double(e), 1 - n);  // -2 e / N
-    double sv, cv;
-    sincospi(x, &sv, &cv);
-    if (t < nlo)
-      tw_lo[t] = make_double2(cv, sv);
-    else
-      tw_hi[t - nlo] = make_double2(cv, sv);
-  }
+__device__ inline void twiddle_entry(double2* __restrict__ tw_hi, double2* __restrict__ tw_lo, int n, int h,
+                                     int64_t t) {
+  int64_t nlo = int64_t(1) << h;
+  int64_t e = t < nlo ? t : ((t - nlo) << h);
+  double x = -ldexp(double(e), 1 - n);  // -2 e / N
+  double sv, cv;
+  sincospi(x, &sv, &cv);
+  if (t < nlo)
+    tw_lo[t] = make_double2(cv, sv);
+  else
+    tw_hi[t - nlo] = make_double2(cv, sv);
 }
 
 // Round a double to the nearest BF16 value (ties to even); returns the BF16
@@ -84,103 +87,87 @@ __device__ inline uint16_t bf16_rne(double x, double* rounded) {
 // plane the layout is blocked by 16 columns: element (row j, col c) sits at
 // ((c / 16) * d + j) * 16 + c % 16, so that a tile of consecutive rows and 16
 // consecutive columns is contiguous.
-__global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
-                                                           int t) {
+__device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e) {
   const int64_t d = int64_t(1) << t;
   const int64_t dd = d * d;
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
-    int64_t j = e >> t, c = e & (d - 1);
-    double2 v = V[e];
-    int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
-    double w[2] = {v.x, v.y};
+  int64_t j = e >> t, c = e & (d - 1);
+  double2 v = V[e];
+  int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
+  double w[2] = {v.x, v.y};
 #pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-      double r0 = w[comp], q0, q1, q2;
-      uint16_t hi = bf16_rne(r0, &q0);
-      double r1 = r0 - q0;
-      uint16_t mid = bf16_rne(r1, &q1);
-      double r2 = r1 - q1;
-      uint16_t lo = bf16_rne(r2, &q2);
-      planes[(0 * 2 + comp) * dd + dst] = hi;
-      planes[(1 * 2 + comp) * dd + dst] = mid;
-      planes[(2 * 2 + comp) * dd + dst] = lo;
-    }
+  for (int comp = 0; comp < 2; ++comp) {
+    double r0 = w[comp], q0, q1, q2;
+    uint16_t hi = bf16_rne(r0, &q0);
+    double r1 = r0 - q0;
+    uint16_t mid = bf16_rne(r1, &q1);
+    double r2 = r1 - q1;
+    uint16_t lo = bf16_rne(r2, &q2);
+    planes[(0 * 2 + comp) * dd + dst] = hi;
+    planes[(1 * 2 + comp) * dd + dst] = mid;
+    planes[(2 * 2 + comp) * dd + dst] = lo;
   }
 }
 
-// Newton-Schulz support: G <- G - I and defect = max(defect, max |G_ij|).
-// The max of non-negative doubles is order-independent, so the atomic on the
-// IEEE bit pattern (monotone for non-negative values) is deterministic.
-__global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G, int d,
-                                                                  unsigned long long* __restrict__ defect_bits) {
+__device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// Newton-Schulz support: G <- G - I over elements [e0, e1) (stride), then
+// defect = max(defect, max |G_ij|). The max of non-negative doubles is
+// order-independent, so the atomic on the IEEE bit pattern (monotone for
+// non-negative values) is deterministic.
+__device__ inline void subi_range(double2* __restrict__ G, int d, int64_t e0, int64_t e1, int64_t stride,
+                                  unsigned long long* __restrict__ defect_bits) {
   __shared__ double red[kThreads / 64];
-  const int64_t dd = int64_t(d) * d;
   double mx = 0.0;
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+  for (int64_t e = e0; e < e1; e += stride) {
     double2 g = G[e];
     if ((e / d) == (e % d)) {
       g.x -= 1.0;
       G[e] = g;
     }
-    double a = sqrt(g.x * g.x + g.y * g.y);
-    mx = (a > mx || a != a) ? a : mx;
+    mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(mx, off);
-    mx = (o > mx || o != o) ? o : mx;
-  }
+  for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / 64; ++w) mx = (red[w] > mx || red[w] != red[w]) ? red[w] : mx;
-    unsigned long long bits = (unsigned long long)__double_as_longlong(mx != mx ? __longlong_as_double(0x7ff0000000000000ll) : mx);
-    atomicMax(defect_bits, bits);
+    for (int w = 1; w < kThreads / 64; ++w) mx = nan_max(mx, red[w]);
+    if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
+    atomicMax(defect_bits, (unsigned long long)__double_as_longlong(mx));
   }
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0ull;
-}
-
-// Readout: P(m(p)) = 2^-n sum_r |X[p][r]|^2 in FP64 (components widened
+// Readout rows: P(m(p)) = 2^-n sum_r |X[p][r]|^2 in FP64 (components widened
 // before squaring). The DFT passes leave out the inverse QFT's 2^(-n/2), so
-// the exact power-of-two 2^-n restores it here. One row per group of
-// G = min(d, 64) lanes; a fixed shuffle tree makes the sum order
-// deterministic.
+// the exact power of two 2^-n restores it here. One row per group of
+// G = min(d, 64) lanes of a wave; a fixed shuffle tree makes the sum order
+// deterministic. `base` is the wave's first row.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_prob(const T* __restrict__ X, double* __restrict__ prob, int n, int t,
-                                                   DftPlan plan, double scale) {
+__device__ inline void prob_rows(const T* __restrict__ X, double* __restrict__ prob, int n, int t,
+                                 const DftPlan& plan, double scale, int64_t base) {
   const int64_t N = int64_t(1) << n;
   const int d = 1 << t;
   const int G = d < 64 ? d : 64;
   const int lane = threadIdx.x & 63;
-  const int rows_per_wave = 64 / G;
-  const int64_t wave = (blockIdx.x * int64_t(kThreads) + threadIdx.x) >> 6;
-  const int64_t nwaves = (int64_t(gridDim.x) * kThreads) >> 6;
-  for (int64_t base = wave * rows_per_wave; base < N; base += nwaves * rows_per_wave) {
-    int64_t p = base + lane / G;
-    int c0 = lane % G;
-    double acc = 0.0;
-    if (p < N) {
-      const T* row = X + p * d;
-      for (int c = c0; c < d; c += G) {
-        T v = row[c];
-        double re = double(v.x), im = double(v.y);
-        acc += re * re + im * im;
-      }
+  int64_t p = base + lane / G;
+  int c0 = lane % G;
+  double acc = 0.0;
+  if (p < N) {
+    const T* row = X + p * d;
+    for (int c = c0; c < d; c += G) {
+      T v = row[c];
+      double re = double(v.x), im = double(v.y);
+      acc += re * re + im * im;
     }
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
   }
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
 }
 
-// Report: prob_sum, ||psi||^2, the defect, and the flags. One block.
-__global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
-                                                     const double2* __restrict__ psi, int t,
-                                                     const unsigned long long* __restrict__ defect_bits,
-                                                     double* __restrict__ report) {
+// Report: prob_sum, ||psi||^2, the defect and the flags, by one block.
+__device__ inline void report_block(const double* __restrict__ prob, int n, const double2* __restrict__ psi, int t,
+                                    const unsigned long long* __restrict__ defect_bits, double* __restrict__ report) {
   __shared__ double red[2][kThreads];
+  __shared__ int any_bad;
   const int64_t N = int64_t(1) << n;
   const int d = 1 << t;
   double s = 0.0, q = 0.0;
@@ -193,7 +180,6 @@ __global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ 
   for (int i = threadIdx.x; i < d; i += kThreads) q += psi[i].x * psi[i].x + psi[i].y * psi[i].y;
   red[0][threadIdx.x] = s;
   red[1][threadIdx.x] = q;
-  __shared__ int any_bad;
   if (threadIdx.x == 0) any_bad = 0;
   __syncthreads();
   if (bad) atomicOr(&any_bad, 1);
@@ -218,6 +204,67 @@ __global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ 
   }
 }
 
+// ------------------------------------------------------ single-instance kernels
+
+__global__ void __launch_bounds__(kThreads) k_h_broadcast_c64(const double2* __restrict__ psi,
+                                                              float4* __restrict__ out, int64_t pairs,
+                                                              int dmask, double scale) {
+  h_range_c64(psi, out, blockIdx.x * int64_t(kThreads) + threadIdx.x, pairs, dmask, scale,
+              int64_t(gridDim.x) * kThreads);
+}
+
+__global__ void __launch_bounds__(kThreads) k_h_broadcast_c128(const double2* __restrict__ psi,
+                                                               double2* __restrict__ out, int64_t total,
+                                                               int dmask, double scale) {
+  h_range_c128(psi, out, blockIdx.x * int64_t(kThreads) + threadIdx.x, total, dmask, scale,
+               int64_t(gridDim.x) * kThreads);
+}
+
+__global__ void __launch_bounds__(kThreads) k_twiddles(double2* __restrict__ tw_hi, double2* __restrict__ tw_lo,
+                                                       int n, int h) {
+  int64_t total = (int64_t(1) << h) + (int64_t(1) << (n - h));
+  for (int64_t t = blockIdx.x * int64_t(kThreads) + threadIdx.x; t < total; t += int64_t(gridDim.x) * kThreads)
+    twiddle_entry(tw_hi, tw_lo, n, h, t);
+}
+
+__global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
+                                                           int t) {
+  const int64_t dd = int64_t(1) << (2 * t);
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
+    split_entry(V, planes, t, e);
+}
+
+__global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G, int d,
+                                                                  unsigned long long* __restrict__ defect_bits) {
+  subi_range(G, d, blockIdx.x * int64_t(kThreads) + threadIdx.x, int64_t(d) * d, int64_t(gridDim.x) * kThreads,
+             defect_bits);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prob(const T* __restrict__ X, double* __restrict__ prob, int n, int t,
+                                                   DftPlan plan, double scale) {
+  const int64_t N = int64_t(1) << n;
+  const int d = 1 << t;
+  const int G = d < 64 ? d : 64;
+  const int rows_per_wave = 64 / G;
+  const int64_t wave = (blockIdx.x * int64_t(kThreads) + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * kThreads) >> 6;
+  for (int64_t base = wave * rows_per_wave; base < N; base += nwaves * rows_per_wave)
+    prob_rows<T>(X, prob, n, t, plan, scale, base);
+}
+
+__global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
+                                                     const double2* __restrict__ psi, int t,
+                                                     const unsigned long long* __restrict__ defect_bits,
+                                                     double* __restrict__ report) {
+  report_block(prob, n, psi, t, defect_bits, report);
+}
+
 // After a stand-alone controlled step (whole state in buf0, updated rows
 // written to `other`), copy the rows with bit k set back into buf0.
 template <typename T>
@@ -229,6 +276,123 @@ __global__ void __launch_bounds__(kThreads) k_copy_rows_back(T* __restrict__ sta
     int64_t c = e & ((int64_t(1) << t) - 1);
     int64_t j = ctrl_row(i, k);
     state[(j << t) + c] = other[(j << t) + c];
+  }
+}
+
+// ----------------------------------------------------------- batch setup
+
+struct DescArgs {
+  int first, count;
+  BatchProblem p[kBatchChunk];
+};
+
+__global__ void k_batch_descs(InstDesc* __restrict__ desc, char* ws, DescArgs a) {
+  int i = threadIdx.x;
+  if (i >= a.count) return;
+  const BatchProblem& p = a.p[i];
+  InstDesc D;
+  D.n = p.n;
+  D.t = p.t;
+  D.U = static_cast<const double2*>(p.U);
+  D.psi = static_cast<const double2*>(p.psi);
+  D.prob = p.prob;
+  D.report = static_cast<double*>(p.report);
+  D.ws = ws + p.ws_offset;
+  desc[a.first + i] = D;
+}
+
+struct TableArgs {
+  int nlaunch;
+  BatchLaunch l[kBatchLaunchChunk];
+};
+
+// One block per launch: its members in instance order and the prefix sums
+// of their workgroup counts.
+__global__ void k_batch_tables(const InstDesc* __restrict__ desc, int ninst, int32_t* __restrict__ tables,
+                               TableArgs a, int mixed, int polar) {
+  if (blockIdx.x >= unsigned(a.nlaunch) || threadIdx.x != 0) return;
+  const BatchLaunch L = a.l[blockIdx.x];
+  int32_t* tab = tables + L.table_off;
+  int count = 0;
+  for (int i = 0; i < ninst; ++i)
+    if (batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, polar != 0) > 0) ++count;
+  tab[0] = count;
+  int c = 0;
+  int64_t run = 0;
+  for (int i = 0; i < ninst; ++i) {
+    int64_t tiles = batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, polar != 0);
+    if (tiles <= 0) continue;
+    tab[1 + c] = i;
+    tab[1 + count + c] = int32_t(run);
+    run += tiles;
+    ++c;
+  }
+  tab[1 + count + count] = int32_t(run);
+}
+
+// --------------------------------------------------------- batched kernels
+
+__device__ inline const double2* power_ptr(const InstDesc& D, const RunLayout& L, int slot) {
+  if (slot == 0) return D.U;
+  return reinterpret_cast<const double2*>(D.ws + (slot == 1 ? L.vbuf : L.tbuf));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, const InstDesc* __restrict__ desc,
+                                                           const int32_t* __restrict__ table, int polar) {
+  constexpr bool mixed = sizeof(T) == 8;
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const RunLayout L = run_layout(D.n, D.t, mixed, polar != 0);
+  const int n = D.n, t = D.t, d = 1 << t;
+  const int64_t N = int64_t(1) << n;
+  unsigned long long* defect = reinterpret_cast<unsigned long long*>(D.ws + L.scratch);
+  switch (kind) {
+    case BK_ZERO:
+      if (threadIdx.x == 0) defect[0] = 0ull;
+      break;
+    case BK_HLAYER: {
+      int64_t e0 = local * kHTile, e1 = min(e0 + int64_t(kHTile), N * d);
+      if (mixed)
+        h_range_c64(D.psi, reinterpret_cast<float4*>(D.ws + L.state0), e0 / 2 + threadIdx.x, e1 / 2, d - 1,
+                    h_scale(n), kThreads);
+      else
+        h_range_c128(D.psi, reinterpret_cast<double2*>(D.ws + L.state0), e0 + threadIdx.x, e1, d - 1, h_scale(n),
+                     kThreads);
+      break;
+    }
+    case BK_TWIDDLE: {
+      const int h = tw_split(n);
+      int64_t e = local * kThreads + threadIdx.x;
+      if (e < (int64_t(1) << h) + (int64_t(1) << (n - h)))
+        twiddle_entry(reinterpret_cast<double2*>(D.ws + L.tw_hi), reinterpret_cast<double2*>(D.ws + L.tw_lo), n, h,
+                      e);
+      break;
+    }
+    case BK_SUBI: {
+      int64_t e0 = local * kSubiTile, e1 = min(e0 + int64_t(kSubiTile), int64_t(d) * d);
+      subi_range(reinterpret_cast<double2*>(D.ws + L.gbuf), d, e0 + threadIdx.x, e1, kThreads, defect);
+      break;
+    }
+    case BK_SPLIT: {
+      const double2* V = power_ptr(D, L, power_slot(step, polar != 0));
+      uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
+      int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e);
+      break;
+    }
+    case BK_PROB: {
+      const int G = d < 64 ? d : 64;
+      const int rows_per_wave = 64 / G;
+      int64_t base = (local * 4 + (threadIdx.x >> 6)) * rows_per_wave;
+      prob_rows<T>(reinterpret_cast<const T*>(D.ws + L.state0), D.prob, n, t, make_dft_plan(n), ldexp(1.0, -n),
+                   base);
+      break;
+    }
+    case BK_REPORT:
+      if (D.report) report_block(D.prob, n, D.psi, t, polar ? defect : nullptr, D.report);
+      break;
   }
 }
 
@@ -305,6 +469,37 @@ hipError_t launch_copy_rows_back(bool mixed, void* state, const void* other, int
   else
     hipLaunchKernelGGL(k_copy_rows_back<double2>, dim3(grid_for(half)), dim3(kThreads), 0, s,
                        static_cast<double2*>(state), static_cast<const double2*>(other), n, t, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_descs(InstDesc* desc, char* ws, const BatchProblem* probs, int first, int count,
+                              hipStream_t s) {
+  DescArgs a{};
+  a.first = first;
+  a.count = count;
+  for (int i = 0; i < count; ++i) a.p[i] = probs[i];
+  hipLaunchKernelGGL(k_batch_descs, dim3(1), dim3(64), 0, s, desc, ws, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables, const BatchLaunch* launches,
+                               int nlaunch, bool mixed, bool polar, hipStream_t s) {
+  TableArgs a{};
+  a.nlaunch = nlaunch;
+  for (int i = 0; i < nlaunch; ++i) a.l[i] = launches[i];
+  hipLaunchKernelGGL(k_batch_tables, dim3(nlaunch), dim3(64), 0, s, desc, ninst, tables, a, mixed ? 1 : 0,
+                     polar ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                                    bool mixed, bool polar, hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_elementwise<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
+                       polar ? 1 : 0);
+  else
+    hipLaunchKernelGGL(kb_elementwise<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
+                       polar ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -87,21 +87,25 @@ __device__ __forceinline__ double2 twiddle(int64_t x, const double2* __restrict_
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Largest LDS exchange buffer of a pass (R1 = R2 = 16): 16 x 16 x 16 points.
+constexpr int kQftLds = 4096;
+
+// Workgroup `block` of one pass; L: LDS scratch of kQftLds points.
 template <typename T, int R1, int R2>
-__global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, const T* __restrict__ buf1, int gather,
-                                                       int n, int t, int pass_bits, int bits_before,
-                                                       const double2* __restrict__ tw_hi,
-                                                       const double2* __restrict__ tw_lo, int h) {
+__device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restrict__ buf1, int gather, int n, int t,
+                                         int pass_bits, int bits_before, const double2* __restrict__ tw_hi,
+                                         const double2* __restrict__ tw_lo, int h, int64_t block,
+                                         T* __restrict__ L) {
   typedef typename Real<T>::type R;
   constexpr int E = kThreads / R2;  // elements per workgroup
   constexpr int L1 = Log2<R1>::v, L2 = Log2<R2>::v;
-  __shared__ T L[R2 > 1 ? R1 * R2 * E : 1];
+  static_assert(R1 * R2 * E <= kQftLds, "LDS exchange buffer");
 
   const int bq_log = n - bits_before;        // rows per block (log2)
   const int m_log = bq_log - pass_bits;      // rows between DFT points (log2)
   const int64_t md = int64_t(1) << (m_log + t);
   const int64_t total_e = int64_t(1) << (n + t - pass_bits);
-  const int64_t f0 = int64_t(blockIdx.x) * E;
+  const int64_t f0 = block * E;
   const int tid = threadIdx.x;
 
   auto element = [&](int e, int64_t& base, int64_t& j2) {
@@ -205,6 +209,47 @@ __global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, con
 }
 
 template <typename T, int R1, int R2>
+__global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, const T* __restrict__ buf1, int gather,
+                                                       int n, int t, int pass_bits, int bits_before,
+                                                       const double2* __restrict__ tw_hi,
+                                                       const double2* __restrict__ tw_lo, int h) {
+  __shared__ T L[R2 > 1 ? R1 * R2 * (kThreads / R2) : 1];
+  qft_tile<T, R1, R2>(buf0, buf1, gather, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, blockIdx.x, L);
+}
+
+// Grouped pass `pass` over the instances of a launch table: each instance
+// runs its own schedule (make_dft_plan of its n), so the radix is chosen
+// per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __restrict__ desc,
+                                                   const int32_t* __restrict__ table, int polar) {
+  constexpr bool mixed = sizeof(T) == 8;
+  __shared__ T L[kQftLds];
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const RunLayout lay = run_layout(D.n, D.t, mixed, polar != 0);
+  const DftPlan plan = make_dft_plan(D.n);
+  int before = 0;
+  for (int q = 0; q < pass; ++q) before += plan.bits[q];
+  T* b0 = reinterpret_cast<T*>(D.ws + lay.state0);
+  const T* b1 = reinterpret_cast<const T*>(D.ws + lay.state1);
+  const double2* hi = reinterpret_cast<const double2*>(D.ws + lay.tw_hi);
+  const double2* lo = reinterpret_cast<const double2*>(D.ws + lay.tw_lo);
+  const int h = tw_split(D.n), g = pass == 0 ? 1 : 0, n = D.n, t = D.t;
+  switch (plan.bits[pass]) {
+    case 1: qft_tile<T, 2, 1>(b0, b1, g, n, t, 1, before, hi, lo, h, local, L); break;
+    case 2: qft_tile<T, 4, 1>(b0, b1, g, n, t, 2, before, hi, lo, h, local, L); break;
+    case 3: qft_tile<T, 8, 1>(b0, b1, g, n, t, 3, before, hi, lo, h, local, L); break;
+    case 4: qft_tile<T, 16, 1>(b0, b1, g, n, t, 4, before, hi, lo, h, local, L); break;
+    case 5: qft_tile<T, 16, 2>(b0, b1, g, n, t, 5, before, hi, lo, h, local, L); break;
+    case 6: qft_tile<T, 16, 4>(b0, b1, g, n, t, 6, before, hi, lo, h, local, L); break;
+    case 7: qft_tile<T, 16, 8>(b0, b1, g, n, t, 7, before, hi, lo, h, local, L); break;
+    case 8: qft_tile<T, 16, 16>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L); break;
+  }
+}
+
+template <typename T, int R1, int R2>
 hipError_t go(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
               const double2* lo, int h, hipStream_t s) {
   constexpr int E = kThreads / R2;
@@ -233,12 +278,14 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
 
 }  // namespace
 
-DftPlan make_dft_plan(int n) {
-  DftPlan p{};
-  p.npass = (n + 7) / 8;
-  int base = n / p.npass, extra = n % p.npass;
-  for (int q = 0; q < p.npass; ++q) p.bits[q] = base + (q < extra ? 1 : 0);
-  return p;
+hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                            bool polar, hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL(kb_qft<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, polar ? 1 : 0);
+  else
+    hipLaunchKernelGGL(kb_qft<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table,
+                       polar ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_qft_pass(bool mixed, void* buf0, const void* buf1, bool gather, int n, int t, int pass_bits,

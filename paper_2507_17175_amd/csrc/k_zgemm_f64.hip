@@ -47,7 +47,7 @@ __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
 }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
+__device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs& g, int tile_m, int tile_n) {
   constexpr int kThreads = 64 * WM * WN;
   static_assert(WM * WN == 4 || WM * WN == 8, "4 or 8 waves");
   constexpr int TM = BM / WM, TN = BN / WN;  // wave tile
@@ -61,9 +61,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
   __shared__ double2 Bs[kBK * PB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
-  const int2 tile = xcd_tile(tiles_m, tiles_n);
-  const int i0 = tile.x * BM, j0 = tile.y * BN;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
   const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
 
   // Per-thread A row pointers (gather mode: rows of the state).
@@ -241,6 +239,79 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
 }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
+  const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN>(a, g, tile.x, tile.y);
+}
+
+// ---- grouped (batched) forms: one launch over the instances of a table ----
+
+// Power-chain products of step k for every instance that takes part, with
+// 32 x 32 tiles: BK_SQ  X_k = V_{k-1} V_{k-1};  BK_GRAM  G = X^H X;
+// BK_CORR  V_k = X - X (G - I) / 2.
+template <int KIND>
+__global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __restrict__ desc,
+                                                const int32_t* __restrict__ table, int mixed, int polar) {
+  constexpr int T = kBatchGemmTile;
+  constexpr int OPA = KIND == BK_GRAM ? OP_C : OP_N;
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const bool pol = polar != 0;
+  const RunLayout L = run_layout(D.n, D.t, mixed != 0, pol);
+  const int d = 1 << D.t;
+  const int tiles_n = int((d + T - 1) / T);
+  double2* vbuf = reinterpret_cast<double2*>(D.ws + L.vbuf);
+  double2* tbuf = reinterpret_cast<double2*>(D.ws + L.tbuf);
+  double2* gbuf = reinterpret_cast<double2*>(D.ws + L.gbuf);
+  ZgemmArgs a{};
+  a.M = a.N = a.K = d;
+  a.lda = a.ldb = a.ldc = a.ldcin = d;
+  a.alpha = make_double2(1.0, 0.0);
+  a.beta = make_double2(0.0, 0.0);
+  if (KIND == BK_SQ) {
+    const int src = power_slot(step - 1, pol);
+    const double2* cur = src == 0 ? D.U : (src == 1 ? vbuf : tbuf);
+    a.A = a.B = cur;
+    a.C = pol ? vbuf : (power_slot(step, pol) == 1 ? vbuf : tbuf);
+  } else if (KIND == BK_GRAM) {
+    a.A = a.B = vbuf;
+    a.C = gbuf;
+  } else {  // BK_CORR
+    a.A = vbuf;
+    a.B = gbuf;
+    a.alpha = make_double2(-0.5, 0.0);
+    a.beta = make_double2(1.0, 0.0);
+    a.Cin = vbuf;
+    a.C = tbuf;
+  }
+  GatherArgs g{};
+  zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+}
+
+// FP64-form controlled step k with 64 x 64 tiles.
+__global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __restrict__ desc,
+                                                   const int32_t* __restrict__ table, int polar) {
+  int64_t local;
+  const int i = find_member(table, blockIdx.x, &local);
+  const InstDesc D = desc[i];
+  const bool pol = polar != 0;
+  const RunLayout L = run_layout(D.n, D.t, false, pol);
+  const int d = 1 << D.t;
+  const int slot = power_slot(step, pol);
+  ZgemmArgs a{};
+  a.M = 1 << (D.n - 1);
+  a.N = a.K = d;
+  a.lda = a.ldb = a.ldc = d;
+  a.B = slot == 0 ? D.U : reinterpret_cast<const double2*>(D.ws + (slot == 1 ? L.vbuf : L.tbuf));
+  GatherArgs g{reinterpret_cast<double2*>(D.ws + L.state0), reinterpret_cast<double2*>(D.ws + L.state1), step,
+               (uint64_t(1) << step) - 1};
+  const int tiles_n = (d + 63) / 64;
+  zgemm_tile<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+}
+
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 hipError_t go(const ZgemmArgs& a, const GatherArgs& g, hipStream_t s) {
   int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
@@ -313,6 +384,31 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
     case 3: return go<OP_N, OP_T, true, 128, 128, 2, 4>(a, g, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                              bool mixed, bool polar, hipStream_t s) {
+  const int m = mixed ? 1 : 0, p = polar ? 1 : 0;
+  switch (kind) {
+    case BK_SQ:
+      hipLaunchKernelGGL(kb_zgemm<BK_SQ>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
+      break;
+    case BK_GRAM:
+      hipLaunchKernelGGL(kb_zgemm<BK_GRAM>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
+      break;
+    case BK_CORR:
+      hipLaunchKernelGGL(kb_zgemm<BK_CORR>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool polar,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(kb_ctrl_f64, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, polar ? 1 : 0);
+  return hipGetLastError();
 }
 
 }  // namespace qpe

@@ -43,42 +43,92 @@ namespace {
 
 using namespace qpe;
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
 
-int tw_split(int n) { return (n + 1) / 2; }
+RunLayout run_layout(int n, int t, int form, unsigned flags) {
+  return qpe::run_layout(n, t, form == QPE_FORM_MIXED, !(flags & QPE_NO_POLAR));
+}
 
-// Workspace regions of one run (byte offsets; 0-size regions are unused).
-struct RunLayout {
-  size_t state0, state1, vbuf, tbuf, gbuf, planes, tw_hi, tw_lo, scratch, total;
+// ---- batched runs -------------------------------------------------------
+//
+// Workspace of a batched run: [launch tables][instance descriptors]
+// [instance 0 region][instance 1 region]... Every region is 256-aligned.
+struct BatchPlan {
+  std::vector<BatchLaunch> launches;
+  std::vector<int64_t> tiles;  // workgroups of each launch
+  size_t table_bytes = 0, desc_off = 0, inst_off = 0, total = 0;
+  std::vector<size_t> inst_base;  // byte offset of each instance region
+  bool ok = true;                 // false if a launch exceeds the grid limit
 };
 
-RunLayout run_layout(int n, int t, int form, unsigned flags) {
-  RunLayout L{};
-  const size_t d = size_t(1) << t, N = size_t(1) << n;
-  const size_t amp = form == QPE_FORM_MIXED ? 8 : 16;
-  const size_t mat = d * d * 16;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off = align_up(off + bytes);
-    return o;
+BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, bool with_report) {
+  BatchPlan P;
+  const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
+  int32_t table_ints = 0;
+  auto add = [&](int kind, int step) {
+    int members = 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i) {
+      int64_t w = batch_tiles(kind, step, p[i].n_meas, p[i].n_mat, mixed, polar);
+      if (w > 0) {
+        ++members;
+        tiles += w;
+      }
+    }
+    if (tiles == 0) return;
+    if (tiles >= (int64_t(1) << 31)) P.ok = false;
+    P.launches.push_back(BatchLaunch{kind, step, table_ints});
+    P.tiles.push_back(tiles);
+    table_ints += 2 + 2 * members;
   };
-  L.state0 = take(N * d * amp);
-  L.state1 = take(N * d * amp);
-  L.vbuf = take(mat);
-  L.tbuf = take(mat);
-  L.gbuf = (flags & QPE_NO_POLAR) ? 0 : take(mat);
-  L.planes = (form == QPE_FORM_MIXED && t >= 5) ? take(6 * d * d * 2) : 0;
-  const int h = tw_split(n);
-  L.tw_hi = take((N >> h) * 16);
-  L.tw_lo = take((size_t(1) << h) * 16);
-  L.scratch = take(64);
-  L.total = off;
-  return L;
+  int maxn = 0, maxpass = 0;
+  for (int i = 0; i < count; ++i) {
+    maxn = p[i].n_meas > maxn ? p[i].n_meas : maxn;
+    int np = make_dft_plan(p[i].n_meas).npass;
+    maxpass = np > maxpass ? np : maxpass;
+  }
+  add(BK_ZERO, 0);
+  add(BK_HLAYER, 0);
+  add(BK_TWIDDLE, 0);
+  for (int k = 0; k < maxn; ++k) {
+    if (k >= 1) {
+      add(BK_SQ, k);
+      if (polar) {
+        add(BK_GRAM, k);
+        add(BK_SUBI, k);
+        add(BK_CORR, k);
+      }
+    }
+    if (mixed) {
+      add(BK_SPLIT, k);
+      add(BK_CTRL_SMALL, k);
+      add(BK_CTRL_M32, k);
+      add(BK_CTRL_M64, k);
+      add(BK_CTRL_M128, k);
+    } else {
+      add(BK_CTRL_SMALL, k);
+      add(BK_CTRL_F64, k);
+    }
+  }
+  for (int q = 0; q < maxpass; ++q) add(BK_QFT, q);
+  add(BK_PROB, 0);
+  if (with_report) add(BK_REPORT, 0);
+  P.table_bytes = align_up(size_t(table_ints) * 4);
+  P.desc_off = P.table_bytes;
+  P.inst_off = P.desc_off + align_up(size_t(count) * sizeof(InstDesc));
+  size_t off = P.inst_off;
+  P.inst_base.resize(count);
+  for (int i = 0; i < count; ++i) {
+    P.inst_base[i] = off;
+    off += run_layout(p[i].n_meas, p[i].n_mat, form, flags).total;
+  }
+  P.total = off;
+  return P;
+}
+
+size_t workspace_need(const qpe_problem* p, int count, int form, unsigned flags) {
+  if (count == 1) return run_layout(p[0].n_meas, p[0].n_mat, form, flags).total;
+  return plan_batch(p, count, form, flags, true).total;
 }
 
 qpe_status check_sizes(int n, int t) {
@@ -137,7 +187,7 @@ struct TimerScope {
   qpe_ctx* ctx;
   long idx = -1;
   TimerScope(qpe_ctx* c, int which) : ctx(c) {
-    if (c->timing && c->timers_used < c->timers.size()) {
+    if (which >= 0 && c->timing && c->timers_used < c->timers.size()) {
       idx = long(c->timers_used++);
       c->timers[idx].which = which;
       (void)hipEventRecord(c->timers[idx].start, c->stream);
@@ -268,6 +318,78 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
                                  reinterpret_cast<double2*>(ws + L.tw_lo));
   if (st != QPE_OK) return st;
   if (report) QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, s));
+  return QPE_OK;
+}
+
+// Batched run: one grouped launch per (stage, step) covers every instance
+// that takes part in it. The descriptors and launch tables are written on
+// the device by setup kernels whose inputs travel as kernel arguments, so
+// the whole sequence can be captured into a HIP graph and replayed.
+int timer_of(int kind) {
+  switch (kind) {
+    case BK_HLAYER: return QPE_TIMER_HLAYER;
+    case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR: return QPE_TIMER_POWERS;
+    case BK_SPLIT: return QPE_TIMER_SPLIT;
+    case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_F64:
+      return QPE_TIMER_CTRL_GEMM;
+    case BK_QFT: return QPE_TIMER_QFT;
+    case BK_PROB: case BK_REPORT: return QPE_TIMER_PROB;
+  }
+  return -1;
+}
+
+qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, unsigned flags, char* ws,
+                     qpe_report* report) {
+  const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
+  hipStream_t s = ctx->stream;
+  const BatchPlan P = plan_batch(p, count, form, flags, true);
+  int32_t* tables = reinterpret_cast<int32_t*>(ws);
+  InstDesc* desc = reinterpret_cast<InstDesc*>(ws + P.desc_off);
+  for (int first = 0; first < count; first += kBatchChunk) {
+    BatchProblem chunk[kBatchChunk];
+    int c = count - first < kBatchChunk ? count - first : kBatchChunk;
+    for (int i = 0; i < c; ++i) {
+      const qpe_problem& q = p[first + i];
+      chunk[i] = BatchProblem{q.n_meas, q.n_mat, q.U, q.psi, q.prob, report ? static_cast<void*>(report + first + i)
+                                                                            : nullptr,
+                              uint64_t(P.inst_base[first + i])};
+    }
+    QPE_HIP(ctx, launch_batch_descs(desc, ws, chunk, first, c, s));
+  }
+  const int nl = int(P.launches.size());
+  for (int first = 0; first < nl; first += kBatchLaunchChunk) {
+    int c = nl - first < kBatchLaunchChunk ? nl - first : kBatchLaunchChunk;
+    QPE_HIP(ctx, launch_batch_tables(desc, count, tables, P.launches.data() + first, c, mixed, polar, s));
+  }
+  for (int l = 0; l < nl; ++l) {
+    const BatchLaunch& L = P.launches[l];
+    const int32_t* tab = tables + L.table_off;
+    const int64_t tiles = P.tiles[l];
+    TimerScope ts(ctx, timer_of(L.kind));
+    switch (L.kind) {
+      case BK_SQ:
+      case BK_GRAM:
+      case BK_CORR:
+        QPE_HIP(ctx, launch_batch_zgemm(L.kind, L.step, desc, tab, tiles, mixed, polar, s));
+        break;
+      case BK_CTRL_SMALL:
+        QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, polar, s));
+        break;
+      case BK_CTRL_M32:
+      case BK_CTRL_M64:
+      case BK_CTRL_M128:
+        QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, polar, s));
+        break;
+      case BK_CTRL_F64:
+        QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, polar, s));
+        break;
+      case BK_QFT:
+        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, polar, s));
+        break;
+      default:
+        QPE_HIP(ctx, launch_batch_elementwise(L.kind, L.step, desc, tab, tiles, mixed, polar, s));
+    }
+  }
   return QPE_OK;
 }
 
@@ -409,14 +531,12 @@ QPE_API qpe_status qpe_workspace_size(const qpe_problem* problems, int count, in
   if (!problems || !bytes || count < 1) return QPE_ERR_ARG;
   qpe_status s = check_form_flags(form, flags);
   if (s != QPE_OK) return s;
-  size_t need = 0;
   for (int i = 0; i < count; ++i) {
     s = check_problem(problems[i], false);
     if (s != QPE_OK) return s;
-    size_t b = run_layout(problems[i].n_meas, problems[i].n_mat, form, flags).total;
-    if (b > need) need = b;
   }
-  *bytes = need;
+  if (count > 1 && !plan_batch(problems, count, form, flags, true).ok) return QPE_ERR_SIZE;
+  *bytes = workspace_need(problems, count, form, flags);
   return QPE_OK;
 }
 
@@ -425,15 +545,13 @@ QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int for
   if (!problems || count < 1) return QPE_ERR_ARG;
   qpe_status s = check_form_flags(form, flags);
   if (s != QPE_OK) return s;
-  size_t need = 0;
   for (int i = 0; i < count; ++i) {
     s = check_problem(problems[i], true);
     if (s != QPE_OK) return s;
-    size_t b = run_layout(problems[i].n_meas, problems[i].n_mat, form, flags).total;
-    if (b > need) need = b;
   }
   if (report && misaligned(report, 8)) return QPE_ERR_ALIGN;
-  return check_workspace(workspace, workspace_bytes, need);
+  if (count > 1 && !plan_batch(problems, count, form, flags, true).ok) return QPE_ERR_SIZE;
+  return check_workspace(workspace, workspace_bytes, workspace_need(problems, count, form, flags));
 }
 
 QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
@@ -444,13 +562,8 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
   ctx->last_error.clear();
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
-  // Instances run one after another on the context stream, sharing the
-  // workspace (stream order separates them).
-  for (int i = 0; i < count; ++i) {
-    s = run_one(ctx, problems[i], form, flags, static_cast<char*>(workspace), report ? report + i : nullptr);
-    if (s != QPE_OK) return s;
-  }
-  return QPE_OK;
+  if (count == 1) return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report);
+  return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report);
 }
 
 // ------------------------------------------------------------ stage entries

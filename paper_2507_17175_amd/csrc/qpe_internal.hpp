@@ -1,6 +1,8 @@
 // Internal declarations shared by the HIP translation units of libqpe.
-// Host-side launchers return the hipError_t of the launch; device helpers are
-// header-inline so each kernel file stays self-contained.
+// Host-side launchers return the hipError_t of the launch; device helpers and
+// the plan functions are header-inline and __host__ __device__, so the host
+// (which sizes grids and workspaces) and the device (which builds the batch
+// tables) evaluate exactly the same formulas.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +24,15 @@ struct DftPlan {
   int npass;
   int bits[8];
 };
+
+// Passes of at most 8 bits (radix 256 = 16 x 16 through LDS), balanced.
+__host__ __device__ inline DftPlan make_dft_plan(int n) {
+  DftPlan p{};
+  p.npass = (n + 7) / 8;
+  int base = n / p.npass, extra = n % p.npass;
+  for (int q = 0; q < p.npass; ++q) p.bits[q] = base + (q < extra ? 1 : 0);
+  return p;
+}
 
 // Row position after the DFT passes -> outcome index m.
 // Digit q of p sits in bits [n - B_{q+1}, n - B_q) of p (B_q = bits[0] + ...
@@ -51,6 +62,169 @@ __host__ __device__ inline int64_t ctrl_row(int64_t i, int k) {
 __host__ __device__ inline int row_parity(int64_t j, uint64_t pmask) {
   return __builtin_popcountll(uint64_t(j) & pmask) & 1;
 }
+
+// ------------------------------------------------------ workspace layout
+
+constexpr size_t kAlign = 256;
+__host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+__host__ __device__ inline int tw_split(int n) { return (n + 1) / 2; }
+
+// Regions of one instance's workspace (byte offsets from its base).
+struct RunLayout {
+  size_t state0, state1, vbuf, tbuf, gbuf, planes, tw_hi, tw_lo, scratch, total;
+};
+
+__host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool polar) {
+  RunLayout L{};
+  const size_t d = size_t(1) << t, N = size_t(1) << n;
+  const size_t amp = mixed ? 8 : 16;
+  const size_t mat = d * d * 16;
+  size_t off = 0;
+  L.state0 = off;
+  off = align_up(off + N * d * amp);
+  L.state1 = off;
+  off = align_up(off + N * d * amp);
+  L.vbuf = off;
+  off = align_up(off + mat);
+  L.tbuf = off;
+  off = align_up(off + mat);
+  L.gbuf = off;
+  if (polar) off = align_up(off + mat);
+  L.planes = off;
+  if (mixed && t >= 5) off = align_up(off + 6 * d * d * 2);
+  const int h = tw_split(n);
+  L.tw_hi = off;
+  off = align_up(off + (N >> h) * 16);
+  L.tw_lo = off;
+  off = align_up(off + (size_t(1) << h) * 16);
+  L.scratch = off;
+  off = align_up(off + 64);
+  L.total = off;
+  return L;
+}
+
+// Where V_k lives during a run: 0 = U itself, 1 = vbuf, 2 = tbuf. With the
+// Newton-Schulz step every square goes to vbuf and the corrected power to
+// tbuf; without it the squares alternate between vbuf (odd k) and tbuf.
+__host__ __device__ inline int power_slot(int k, bool polar) {
+  if (k == 0) return 0;
+  if (polar) return 2;
+  return (k & 1) ? 1 : 2;
+}
+
+// ------------------------------------------------------------- batching
+//
+// A batched run enqueues one grouped launch per (kind, step): every instance
+// that takes part contributes batch_tiles(...) workgroups, and a per-launch
+// table (count, members[count], prefix[count+1]) maps a workgroup to its
+// instance and local tile. The tables are built on the device from the
+// instance descriptors, so nothing is copied from the host.
+
+enum BatchKind {
+  BK_ZERO = 0,
+  BK_HLAYER,
+  BK_TWIDDLE,
+  BK_SQ,
+  BK_GRAM,
+  BK_SUBI,
+  BK_CORR,
+  BK_SPLIT,
+  BK_CTRL_SMALL,
+  BK_CTRL_M32,
+  BK_CTRL_M64,
+  BK_CTRL_M128,
+  BK_CTRL_F64,
+  BK_QFT,
+  BK_PROB,
+  BK_REPORT,
+  BK_COUNT
+};
+
+constexpr int kHTile = 4096;     // complex amplitudes per H-layer tile
+constexpr int kSplitTile = 4096; // operator elements per split tile
+constexpr int kSubiTile = 16384; // operator elements per identity-subtraction tile
+constexpr int kBatchGemmTile = 32;
+
+struct InstDesc {
+  int32_t n, t;
+  const double2* U;
+  const double2* psi;
+  double* prob;
+  double* report;  // 4 doubles, or null
+  char* ws;        // this instance's region of the workspace
+};
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workgroups instance (n, t) contributes to launch (kind, step); 0 if it
+// takes no part. step = controlled step k, or the DFT pass index.
+__host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t, bool mixed, bool polar) {
+  const int64_t N = int64_t(1) << n, d = int64_t(1) << t, half = N / 2;
+  switch (kind) {
+    case BK_ZERO:
+      return 1;
+    case BK_HLAYER:
+      return cdiv(N * d, kHTile);
+    case BK_TWIDDLE: {
+      int h = tw_split(n);
+      return cdiv((int64_t(1) << h) + (int64_t(1) << (n - h)), 256);
+    }
+    case BK_SQ:
+      return (step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
+    case BK_GRAM:
+    case BK_CORR:
+      return (polar && step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
+    case BK_SUBI:
+      return (polar && step >= 1 && step < n) ? cdiv(d * d, kSubiTile) : 0;
+    case BK_SPLIT:
+      return (mixed && t >= 5 && step < n) ? cdiv(d * d, kSplitTile) : 0;
+    case BK_CTRL_SMALL:
+      return (t <= 4 && step < n) ? cdiv(half, 256) : 0;
+    case BK_CTRL_M32:
+      return (mixed && t == 5 && step < n) ? cdiv(half, 128) * (d / 32) : 0;
+    case BK_CTRL_M64:
+      return (mixed && t == 6 && step < n) ? cdiv(half, 128) * (d / 64) : 0;
+    case BK_CTRL_M128:
+      return (mixed && t >= 7 && step < n) ? cdiv(half, 128) * (d / 128) : 0;
+    case BK_CTRL_F64:
+      return (!mixed && t >= 5 && step < n) ? cdiv(half, 64) * cdiv(d, 64) : 0;
+    case BK_QFT: {
+      DftPlan pl = make_dft_plan(n);
+      if (step >= pl.npass) return 0;
+      int b = pl.bits[step];
+      int r2 = b > 4 ? (1 << (b - 4)) : 1;
+      return cdiv((N * d) >> b, 256 / r2);
+    }
+    case BK_PROB: {
+      int64_t G = d < 64 ? d : 64;
+      return cdiv(N, 4 * (64 / G));
+    }
+    case BK_REPORT:
+      return 1;
+  }
+  return 0;
+}
+
+// Instance and local tile of workgroup `tile` in a launch table.
+__device__ inline int find_member(const int32_t* __restrict__ tab, int64_t tile, int64_t* local) {
+  const int count = tab[0];
+  const int32_t* mem = tab + 1;
+  const int32_t* pre = tab + 1 + count;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  *local = tile - pre[lo];
+  return mem[lo];
+}
+
+struct BatchLaunch {
+  int32_t kind, step, table_off;  // table_off in int32 units
+};
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s);
@@ -101,6 +275,34 @@ hipError_t launch_qft_pass(bool mixed, void* buf0, const void* buf1, bool gather
                            int pass_bits, int bits_before, const double2* tw_hi, const double2* tw_lo,
                            int h, hipStream_t s);
 
-DftPlan make_dft_plan(int n);
+// ---- batched launchers: one grouped launch over the instances of a table ----
+struct BatchProblem {
+  int32_t n, t;
+  const void* U;
+  const void* psi;
+  double* prob;
+  void* report;
+  uint64_t ws_offset;
+};
+constexpr int kBatchChunk = 48;  // problems per descriptor-setup launch
+constexpr int kBatchLaunchChunk = 160;
+hipError_t launch_batch_descs(InstDesc* desc, char* ws, const BatchProblem* probs, int first, int count,
+                              hipStream_t s);
+hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables, const BatchLaunch* launches,
+                               int nlaunch, bool mixed, bool polar, hipStream_t s);
+// Elementwise kinds (zero, H layer, twiddles, identity subtraction, split,
+// readout, report).
+hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                                    bool mixed, bool polar, hipStream_t s);
+hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                              bool mixed, bool polar, hipStream_t s);
+hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool polar,
+                                 hipStream_t s);
+hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                                   bool polar, hipStream_t s);
+hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                   bool polar, hipStream_t s);
+hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                            bool polar, hipStream_t s);
 
 }  // namespace qpe

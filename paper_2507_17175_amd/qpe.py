@@ -377,6 +377,7 @@ class Runner:
 
     def __call__(self) -> List[torch.Tensor]:
         L = load_library()
+        self.ctx.bind_current_stream()  # the capture stream while a graph is recorded
         _check(L.qpe_run(self.ctx.handle, self.arr, self.count, self.form, self.flags, self.workspace.data_ptr(),
                          self.workspace.numel(),
                          self.report_buf.data_ptr() if self.report_buf is not None else None),
@@ -395,3 +396,28 @@ def kernel_variants(kernel_class: str) -> int:
     c = ctypes.c_int()
     _check(load_library().qpe_kernel_variants(KERNEL_CLASSES[kernel_class], ctypes.byref(c)), "qpe_kernel_variants")
     return c.value
+
+
+class CapturedRun:
+    """A Runner captured once into a HIP graph (through torch.cuda.CUDAGraph)
+    and replayed: every launch of the batched run, including the device-side
+    setup of descriptors and tables, is a graph node, so a replay costs one
+    graph launch. Outputs are the Runner's tensors, rewritten by each replay."""
+
+    def __init__(self, runner: Runner, warmup: int = 1):
+        self.runner = runner
+        side = torch.cuda.Stream(runner.dev)
+        side.wait_stream(torch.cuda.current_stream(runner.dev))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                runner()
+        torch.cuda.current_stream(runner.dev).wait_stream(side)
+        torch.cuda.synchronize(runner.dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            runner()
+        torch.cuda.synchronize(runner.dev)
+
+    def __call__(self) -> List[torch.Tensor]:
+        self.graph.replay()
+        return self.runner.probs

@@ -61,9 +61,11 @@ def test_workspace_size(L):
     mixed = out.value
     assert L.qpe_workspace_size(_problems([(16, 10)]), 1, 0, 0, ctypes.byref(out)) == 0
     assert out.value > mixed  # complex128 state
-    # batch: the largest instance
+    # batch: every instance gets its own region, plus launch tables and
+    # descriptors in front of them
     assert L.qpe_workspace_size(_problems([(8, 2), (16, 10)]), 2, 1, 0, ctypes.byref(out)) == 0
-    assert out.value == mixed
+    assert out.value >= mixed + small
+    assert out.value <= mixed + small + (1 << 20)
 
 
 @pytest.mark.parametrize("n,t,code", [(0, 2, 2), (31, 2, 2), (8, -1, 2), (8, 16, 2), (30, 10, 2), (20, 14, 0)])

@@ -1,0 +1,108 @@
+"""GPU parity of the batched path (many uneven QPE instances per run).
+
+A batched run uses the same tile code as single runs, so its probabilities
+must equal the single-instance results bit for bit; each instance is also
+checked against the oracle (gate route for general inputs, the Fejer closed
+form for eigenvector inputs) at the tolerances of test_gpu_parity.py.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.qpe_oracle as O
+from tests.libutil import ensure_built
+from workloads import analytic_problem, config_problems, haar_unitary, make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qpe():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ensure_built()
+    from paper_2507_17175_amd import qpe as q
+    q.load_library()
+    return q
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.complex128).cuda()
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+SHAPES = [(1, 0), (2, 1), (3, 2), (5, 3), (7, 4), (9, 5), (8, 6), (10, 7), (9, 8), (12, 2), (6, 9), (4, 5),
+          (11, 4), (8, 8)]
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_uneven_matches_single_and_oracle(qpe, form):
+    say("batch uneven", form, SHAPES)
+    rng = np.random.default_rng(900)
+    probs = []
+    for n, t in SHAPES:
+        d = 1 << t
+        U = haar_unitary(d, rng)
+        psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        psi /= np.linalg.norm(psi)
+        probs.append((U, psi, n))
+    dev_probs = [(dev(U), dev(psi), n) for U, psi, n in probs]
+    batch, rep = qpe.run_batch(dev_probs, form, report=True)
+    tol = 1e-6 if form == "mixed" else 1e-12
+    for (U, psi, n), (Ud, pd, _), Pb, r in zip(probs, dev_probs, batch, rep):
+        Pb = host(Pb)
+        single = host(qpe.run(Ud, pd, n, form))
+        assert np.array_equal(Pb, single), (n, U.shape[0])
+        assert np.abs(Pb - O.qpe_probs(U, psi, n)).max() < tol, (n, U.shape[0])
+        assert r["flags"] == 0 and abs(r["prob_sum"] - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_no_polar_analytic(qpe, form):
+    cases = [(2, 4, 3), (3, 5, 5), (4, 6, 11), (1, 3, 1), (5, 6, 17)]
+    say("batch analytic no-polar", form, cases)
+    problems = [analytic_problem(n, t, j) for t, n, j in cases]
+    out = qpe.run_batch([(dev(p.U), dev(p.psi), p.n_meas) for p in problems], form, flags=qpe.NO_POLAR)
+    for (t, n, j), P in zip(cases, out):
+        P = host(P)
+        assert abs(P[j << (n - t)] - 1.0) < (1e-6 if form == "mixed" else 1e-10)
+
+
+def test_config4_full_batch(qpe):
+    problems = config_problems("c4")
+    say("batch c4 full: 512 instances, t in 3..8, n in 8..16 (mixed)")
+    out, rep = qpe.run_batch([(dev(p.U), dev(p.psi), p.n_meas) for p in problems], "mixed", report=True)
+    worst = 0.0
+    for p, P in zip(problems, out):
+        worst = max(worst, float(np.abs(host(P) - O.fejer(p.phis[0], p.n_meas)).max()))
+    say("c4 max|dP| vs Fejer", worst)
+    assert worst < 1e-6
+    assert np.all(rep["flags"] == 0)
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_graph_replay_matches_eager(qpe, form):
+    probs = config_problems("c4", count=24)
+    say("graph capture of a 24-instance batch", form)
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    runner = qpe.Runner(items, form=form)
+    eager = [host(P).copy() for P in runner()]
+    graph = qpe.CapturedRun(runner)
+    for rep in range(3):
+        for P in runner.probs:
+            P.fill_(-1.0)
+        # eager work on the same stream between replays
+        host(qpe.run(items[0][0], items[0][1], items[0][2], form))
+        out = graph()
+        for e, P in zip(eager, out):
+            assert np.array_equal(host(P), e), rep
