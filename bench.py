@@ -63,7 +63,59 @@ CONFIGS = {
     "c1": "qpe-n8-t2 (Haar 4x4, exact-bit eigenphase k/256, eigenvector input)",
     "c2": "qpe-n16-t10 (Haar 1024x1024, uniform eigenphase, eigenvector input)",
     "c3": "qpe-n20-t8 (Haar 256x256, 3 eigenphases within 2^-18, superposed eigenvectors)",
+    "c4": "qpe-batch-512 (512 instances, t uniform in 3..8, n uniform in 8..16, Haar, eigenvector inputs)",
 }
+
+
+def bench_batch(a, qpe, torch, config_problems):
+    """Batched workload: all instances in one qpe_run (grouped launches),
+    timed eagerly and as a replayed HIP graph."""
+    probs = config_problems(a.config)
+    items = [(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas) for p in probs]
+    run = qpe.Runner(items, form="mixed")
+    for _ in range(a.warmup):
+        run()
+    torch.cuda.synchronize()
+    run.ctx.enable_timing(400 * a.steps + 512)
+    run.ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timing = run.ctx.read_timing()
+    run.ctx.reset_timing()
+    graph = qpe.CapturedRun(run)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        graph()
+    torch.cuda.synchronize()
+    el_g = time.perf_counter() - t0
+    rep = run.reports()
+    count = len(probs)
+    flops = sum(4.0 * p.n_meas * (1 << p.n_meas) * (1 << p.n_mat) ** 2 for p in probs)
+    g_cnt, g_ms = timing["ctrl_gemm"]
+    out = {
+        "metric": "QPE circuits/s (mixed form, batched)",
+        "value": round(count * a.steps / el_g, 2),
+        "unit": "circuits/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * el_g / a.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
+        "data": "synthetic (seeded Haar unitaries, eigenvector inputs)",
+        "config": {"workload": CONFIGS[a.config], "instances": count, "form": "mixed", "graph": True},
+        "eager_ms_per_step": round(1e3 * el / a.steps, 3),
+        "ctrl_gemm": {"algorithmic_flops_per_step": flops, "ms_per_step": round(g_ms / a.steps, 3),
+                      "achieved_tflops": round(flops / (g_ms / a.steps / 1e3) / 1e12, 2),
+                      "launches_per_step": g_cnt // a.steps},
+        "breakdown": {k: {"launches": c // a.steps, "ms_per_step": round(ms / a.steps, 4)}
+                      for k, (c, ms) in timing.items()},
+        "reports": {"flags_nonzero": int(np.count_nonzero(rep["flags"])),
+                    "max_abs_prob_sum_minus_1": float(np.abs(rep["prob_sum"] - 1.0).max())},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def parse():
@@ -94,8 +146,8 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
-def time_form(qpe, torch, prob, form, steps, warmup):
-    run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])], form=form)
+def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
+    run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])], form=form, flags=flags)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -127,6 +179,8 @@ def main():
 
     qpe.load_library()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if a.config == "c4":
+        return bench_batch(a, qpe, torch, config_problems)
     p = config_problems(a.config)[0]
     n, t = p.n_meas, p.n_mat
     N, d = 1 << n, 1 << t
@@ -170,6 +224,19 @@ def main():
         "report_mixed": {"prob_sum": float(rep["prob_sum"]), "unitarity_defect": float(rep["unitarity_defect"]),
                          "flags": int(rep["flags"])},
         "hbm_state_gbs": round((n * N * d * 8 + 3 * N * d * 8) / (ms_per / 1e3) / 1e9, 1),
+    }
+
+    # Prefix-doubling form of the controlled stage (same probabilities, bit
+    # for bit): rows [2^k, 2^(k+1)) = rows [0, 2^k) V_k^T, 2^n - 1 row
+    # products instead of n 2^(n-1).
+    el_d, timing_d, rep_d, P_dbl = time_form(qpe, torch, prob, "mixed", a.steps, 1, flags=qpe.PREFIX_DOUBLING)
+    dc, dms = timing_d["ctrl_gemm"]
+    out["prefix_doubling_form"] = {
+        "circuits_per_s": round(a.steps / el_d, 3), "ms_per_circuit": round(1e3 * el_d / a.steps, 3),
+        "ctrl_algorithmic_flops_per_circuit": 8.0 * (N - 1) * d * d,
+        "ctrl_ms_per_circuit": round(dms / a.steps, 4),
+        "bitwise_equal_to_gate_route": bool(np.array_equal(P_dbl, P_mixed)),
+        "breakdown": {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing_d.items()},
     }
 
     if not a.no_fp64:

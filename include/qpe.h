@@ -67,7 +67,14 @@ enum {
   /* Skip the Newton-Schulz re-unitarisation of the powers. Required when U
    * is not unitary (the paper's analytic test problem, section 3, builds
    * U = P Lambda P^-1 with a non-unitary P). */
-  QPE_NO_POLAR = 1u << 0
+  QPE_NO_POLAR = 1u << 0,
+  /* Prefix-doubling form of the controlled stage. The measurement register
+   * starts in |0...0> (Fig. 1), so after the H layer and the controlled
+   * steps for bits below k, rows [2^k, 2^(k+1)) of the state equal rows
+   * [0, 2^k) times V_k^T. With this flag step k computes exactly those rows
+   * from rows [0, 2^k): 2^n - 1 row products instead of n 2^(n-1), each row
+   * receiving the same sequence of products as in the gate route. Same P. */
+  QPE_PREFIX_DOUBLING = 1u << 1
 };
 
 /* Report flags (qpe_report.flags). */

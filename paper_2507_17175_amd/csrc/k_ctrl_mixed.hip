@@ -100,8 +100,8 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const
     for (int v = 0; v < 16; ++v) {
       int gi = row0 + 32 * x + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       if (gi >= M) continue;
-      int64_t j = ctrl_row(gi, k);
-      float2* dst = (row_parity(j, pmask) ? buf0 : buf1) + j * d + col0 + (lane & 31);
+      int64_t j = step_row(gi, k, pmask);
+      float2* dst = (src_buffer(j, pmask) ? buf0 : buf1) + j * d + col0 + (lane & 31);
 #pragma unroll
       for (int y = 0; y < FN; ++y) dst[32 * y] = make_float2(acc_re[x][y][v], acc_im[x][y][v]);
     }
@@ -142,8 +142,8 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
   for (int q = 0; q < CA; ++q) {
     int c = tid + q * NT;
     int gi = min(i0 + c / 4, M - 1);
-    int64_t j = ctrl_row(gi, k);
-    src_row[q] = (row_parity(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
   }
 
   float4 ra[CA][2];
@@ -285,8 +285,8 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
   for (int q = 0; q < CA; ++q) {
     int c = tid + q * NT;
     int gi = min(i0 + c / 4, M - 1);
-    int64_t j = ctrl_row(gi, k);
-    src_row[q] = (row_parity(j, pmask) ? buf1 : buf0) + j * d;
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d;
   }
 
   float4 ra[CA][4];
@@ -406,24 +406,28 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 // shape follows the operator size class of the launch (d = 32, 64, >= 128).
 template <int KIND>
 __global__ void __launch_bounds__(KIND == BK_CTRL_M32 ? 256 : 512)
-kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int polar) {
+kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags) {
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const RunLayout L = run_layout(D.n, D.t, true, polar != 0);
+  const bool dbl = (bflags & kBatchDoubling) != 0;
+  const RunLayout L = run_layout(D.n, D.t, true, (bflags & kBatchPolar) != 0);
   float2* s0 = reinterpret_cast<float2*>(D.ws + L.state0);
-  float2* s1 = reinterpret_cast<float2*>(D.ws + L.state1);
+  // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0, as a
+  // k+1 qubit register whose second buffer starts at row 2^k
+  float2* s1 = dbl ? s0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<float2*>(D.ws + L.state1);
   const uint16_t* planes = reinterpret_cast<const uint16_t*>(D.ws + L.planes);
-  const uint64_t pmask = (uint64_t(1) << step) - 1;
+  const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
+  const int n = dbl ? step + 1 : D.n;
   constexpr int BN = KIND == BK_CTRL_M32 ? 32 : (KIND == BK_CTRL_M64 ? 64 : 128);
   const int tiles_n = (1 << D.t) / BN;
   const int tm = int(local / tiles_n), tn = int(local % tiles_n);
   if constexpr (KIND == BK_CTRL_M32)
-    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
   else if constexpr (KIND == BK_CTRL_M64)
-    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
   else
-    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, D.n, D.t, step, pmask, tm, tn);
+    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
 }
 
 template <int NT, typename K>
@@ -454,8 +458,8 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
 }
 
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                   bool polar, hipStream_t s) {
-  const int p = polar ? 1 : 0;
+                                   int bflags, hipStream_t s) {
+  const int p = bflags;
   switch (kind) {
     case BK_CTRL_M32:
       hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M32>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, p);

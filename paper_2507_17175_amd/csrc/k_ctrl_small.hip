@@ -30,8 +30,8 @@ __device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restr
   }
   __syncthreads();
   for (int64_t i = i0; i < i1; i += stride) {
-    int64_t j = ctrl_row(i, k);
-    int p = row_parity(j, pmask);
+    int64_t j = step_row(i, k, pmask);
+    int p = src_buffer(j, pmask);
     const T* src = (p ? buf1 : buf0) + j * D;
     T* dst = (p ? buf0 : buf1) + j * D;
     R xr[D], xi[D];
@@ -74,19 +74,20 @@ __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T
 // 256 gathered rows per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDesc* __restrict__ desc,
-                                                          const int32_t* __restrict__ table, int polar) {
+                                                          const int32_t* __restrict__ table, int bflags) {
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const bool pol = polar != 0;
+  const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed, pol);
   const int slot = power_slot(step, pol);
   const double2* V = slot == 0 ? D.U : reinterpret_cast<const double2*>(D.ws + (slot == 1 ? L.vbuf : L.tbuf));
   T* b0 = reinterpret_cast<T*>(D.ws + L.state0);
-  T* b1 = reinterpret_cast<T*>(D.ws + L.state1);
-  const uint64_t pmask = (uint64_t(1) << step) - 1;
-  const int64_t M = int64_t(1) << (D.n - 1);
+  // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0
+  T* b1 = dbl ? b0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<T*>(D.ws + L.state1);
+  const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
+  const int64_t M = int64_t(1) << (dbl ? step : D.n - 1);
   const int64_t i0 = local * kThreads + threadIdx.x;
   switch (D.t) {
     case 0: ctrl_small_rows<T, 1>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
@@ -128,13 +129,13 @@ hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* 
 }
 
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                                   bool polar, hipStream_t s) {
+                                   int bflags, hipStream_t s) {
   if (mixed)
     hipLaunchKernelGGL(kb_ctrl_small<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
-                       polar ? 1 : 0);
+                       bflags);
   else
     hipLaunchKernelGGL(kb_ctrl_small<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
-                       polar ? 1 : 0);
+                       bflags);
   return hipGetLastError();
 }
 

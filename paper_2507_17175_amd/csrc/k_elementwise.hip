@@ -213,6 +213,10 @@ __global__ void __launch_bounds__(kThreads) k_h_broadcast_c64(const double2* __r
               int64_t(gridDim.x) * kThreads);
 }
 
+__global__ void k_h_single_c64(const double2* __restrict__ psi, float2* __restrict__ out, double scale) {
+  if (threadIdx.x == 0) out[0] = make_float2(float(psi[0].x * scale), float(psi[0].y * scale));
+}
+
 __global__ void __launch_bounds__(kThreads) k_h_broadcast_c128(const double2* __restrict__ psi,
                                                                double2* __restrict__ out, int64_t total,
                                                                int dmask, double scale) {
@@ -309,18 +313,21 @@ struct TableArgs {
 // One block per launch: its members in instance order and the prefix sums
 // of their workgroup counts.
 __global__ void k_batch_tables(const InstDesc* __restrict__ desc, int ninst, int32_t* __restrict__ tables,
-                               TableArgs a, int mixed, int polar) {
+                               TableArgs a, int mixed, int bflags) {
   if (blockIdx.x >= unsigned(a.nlaunch) || threadIdx.x != 0) return;
   const BatchLaunch L = a.l[blockIdx.x];
   int32_t* tab = tables + L.table_off;
   int count = 0;
   for (int i = 0; i < ninst; ++i)
-    if (batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, polar != 0) > 0) ++count;
+    if (batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
+                    bflags & kBatchDoubling) > 0)
+      ++count;
   tab[0] = count;
   int c = 0;
   int64_t run = 0;
   for (int i = 0; i < ninst; ++i) {
-    int64_t tiles = batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, polar != 0);
+    int64_t tiles = batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
+                                bflags & kBatchDoubling);
     if (tiles <= 0) continue;
     tab[1 + c] = i;
     tab[1 + count + c] = int32_t(run);
@@ -339,12 +346,13 @@ __device__ inline const double2* power_ptr(const InstDesc& D, const RunLayout& L
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, const InstDesc* __restrict__ desc,
-                                                           const int32_t* __restrict__ table, int polar) {
+                                                           const int32_t* __restrict__ table, int bflags) {
+  const bool polar = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const RunLayout L = run_layout(D.n, D.t, mixed, polar != 0);
+  const RunLayout L = run_layout(D.n, D.t, mixed, polar);
   const int n = D.n, t = D.t, d = 1 << t;
   const int64_t N = int64_t(1) << n;
   unsigned long long* defect = reinterpret_cast<unsigned long long*>(D.ws + L.scratch);
@@ -353,7 +361,8 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       if (threadIdx.x == 0) defect[0] = 0ull;
       break;
     case BK_HLAYER: {
-      int64_t e0 = local * kHTile, e1 = min(e0 + int64_t(kHTile), N * d);
+      // the prefix-doubling form only needs row 0
+      int64_t e0 = local * kHTile, e1 = min(e0 + int64_t(kHTile), dbl ? int64_t(d) : N * d);
       if (mixed)
         h_range_c64(D.psi, reinterpret_cast<float4*>(D.ws + L.state0), e0 / 2 + threadIdx.x, e1 / 2, d - 1,
                     h_scale(n), kThreads);
@@ -376,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       break;
     }
     case BK_SPLIT: {
-      const double2* V = power_ptr(D, L, power_slot(step, polar != 0));
+      const double2* V = power_ptr(D, L, power_slot(step, polar));
       uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
       int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
       for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e);
@@ -398,8 +407,17 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
 
 }  // namespace
 
-hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s) {
-  const int64_t total = int64_t(1) << (n + t);
+hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s,
+                              bool first_row_only) {
+  // first_row_only: write row 0 only (the prefix-doubling form), still
+  // scaled by 2^(-n/2).
+  const int64_t total = int64_t(1) << (first_row_only ? t : n + t);
+  if (mixed && total == 1) {
+    // a single complex64 amplitude cannot use the float4 pair writes
+    hipLaunchKernelGGL(k_h_single_c64, dim3(1), dim3(64), 0, s, static_cast<const double2*>(psi),
+                       static_cast<float2*>(state), std::ldexp(1.0, -(n / 2)) * ((n & 1) ? std::sqrt(0.5) : 1.0));
+    return hipGetLastError();
+  }
   const double scale = std::ldexp(1.0, -(n / 2)) * ((n & 1) ? std::sqrt(0.5) : 1.0);
   if (mixed) {
     // total >= 2 because n >= 1
@@ -483,23 +501,22 @@ hipError_t launch_batch_descs(InstDesc* desc, char* ws, const BatchProblem* prob
 }
 
 hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables, const BatchLaunch* launches,
-                               int nlaunch, bool mixed, bool polar, hipStream_t s) {
+                               int nlaunch, bool mixed, int bflags, hipStream_t s) {
   TableArgs a{};
   a.nlaunch = nlaunch;
   for (int i = 0; i < nlaunch; ++i) a.l[i] = launches[i];
-  hipLaunchKernelGGL(k_batch_tables, dim3(nlaunch), dim3(64), 0, s, desc, ninst, tables, a, mixed ? 1 : 0,
-                     polar ? 1 : 0);
+  hipLaunchKernelGGL(k_batch_tables, dim3(nlaunch), dim3(64), 0, s, desc, ninst, tables, a, mixed ? 1 : 0, bflags);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                    bool mixed, bool polar, hipStream_t s) {
+                                    bool mixed, int bflags, hipStream_t s) {
   if (mixed)
     hipLaunchKernelGGL(kb_elementwise<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
-                       polar ? 1 : 0);
+                       bflags);
   else
     hipLaunchKernelGGL(kb_elementwise<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
-                       polar ? 1 : 0);
+                       bflags);
   return hipGetLastError();
 }
 

@@ -222,13 +222,13 @@ __global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, con
 // per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __restrict__ desc,
-                                                   const int32_t* __restrict__ table, int polar) {
+                                                   const int32_t* __restrict__ table, int bflags) {
   constexpr bool mixed = sizeof(T) == 8;
   __shared__ T L[kQftLds];
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const RunLayout lay = run_layout(D.n, D.t, mixed, polar != 0);
+  const RunLayout lay = run_layout(D.n, D.t, mixed, (bflags & kBatchPolar) != 0);
   const DftPlan plan = make_dft_plan(D.n);
   int before = 0;
   for (int q = 0; q < pass; ++q) before += plan.bits[q];
@@ -236,7 +236,9 @@ __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __r
   const T* b1 = reinterpret_cast<const T*>(D.ws + lay.state1);
   const double2* hi = reinterpret_cast<const double2*>(D.ws + lay.tw_hi);
   const double2* lo = reinterpret_cast<const double2*>(D.ws + lay.tw_lo);
-  const int h = tw_split(D.n), g = pass == 0 ? 1 : 0, n = D.n, t = D.t;
+  // the gate route's state sits in two buffers after the controlled steps
+  const int g = (pass == 0 && !(bflags & kBatchDoubling)) ? 1 : 0;
+  const int h = tw_split(D.n), n = D.n, t = D.t;
   switch (plan.bits[pass]) {
     case 1: qft_tile<T, 2, 1>(b0, b1, g, n, t, 1, before, hi, lo, h, local, L); break;
     case 2: qft_tile<T, 4, 1>(b0, b1, g, n, t, 2, before, hi, lo, h, local, L); break;
@@ -279,12 +281,11 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
 }  // namespace
 
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                            bool polar, hipStream_t s) {
+                            int bflags, hipStream_t s) {
   if (mixed)
-    hipLaunchKernelGGL(kb_qft<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, polar ? 1 : 0);
+    hipLaunchKernelGGL(kb_qft<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, bflags);
   else
-    hipLaunchKernelGGL(kb_qft<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table,
-                       polar ? 1 : 0);
+    hipLaunchKernelGGL(kb_qft<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, bflags);
   return hipGetLastError();
 }
 

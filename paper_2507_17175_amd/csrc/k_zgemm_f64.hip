@@ -88,8 +88,8 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
       const int ci = min(gi, a.M - 1), ck = min(gk, a.K - 1);
       double2 v;
       if (GATHER) {
-        int64_t j = ctrl_row(ci, g.k);
-        v = pick(g, row_parity(j, g.pmask))[j * a.lda + ck];
+        int64_t j = step_row(ci, g.k, g.pmask);
+        v = pick(g, src_buffer(j, g.pmask))[j * a.lda + ck];
       } else if (OPA == OP_N) {
         v = a.A[int64_t(ci) * a.lda + ck];
       } else {
@@ -221,8 +221,8 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
         if (gi >= a.M || gj >= a.N) continue;
         double re = acc_re[x][y][v], im = acc_im[x][y][v];
         if (GATHER) {
-          int64_t j = ctrl_row(gi, g.k);
-          double2* dst = pick(g, 1 - row_parity(j, g.pmask));
+          int64_t j = step_row(gi, g.k, g.pmask);
+          double2* dst = pick(g, 1 - src_buffer(j, g.pmask));
           dst[j * a.ldc + gj] = make_double2(re, im);
         } else {
           double2 o;
@@ -252,13 +252,13 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
 // BK_CORR  V_k = X - X (G - I) / 2.
 template <int KIND>
 __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __restrict__ desc,
-                                                const int32_t* __restrict__ table, int mixed, int polar) {
+                                                const int32_t* __restrict__ table, int mixed, int bflags) {
   constexpr int T = kBatchGemmTile;
   constexpr int OPA = KIND == BK_GRAM ? OP_C : OP_N;
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const bool pol = polar != 0;
+  const bool pol = (bflags & kBatchPolar) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed != 0, pol);
   const int d = 1 << D.t;
   const int tiles_n = int((d + T - 1) / T);
@@ -292,21 +292,23 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
 
 // FP64-form controlled step k with 64 x 64 tiles.
 __global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __restrict__ desc,
-                                                   const int32_t* __restrict__ table, int polar) {
+                                                   const int32_t* __restrict__ table, int bflags) {
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const bool pol = polar != 0;
+  const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, false, pol);
   const int d = 1 << D.t;
   const int slot = power_slot(step, pol);
   ZgemmArgs a{};
-  a.M = 1 << (D.n - 1);
+  a.M = dbl ? (1 << step) : (1 << (D.n - 1));
   a.N = a.K = d;
   a.lda = a.ldb = a.ldc = d;
   a.B = slot == 0 ? D.U : reinterpret_cast<const double2*>(D.ws + (slot == 1 ? L.vbuf : L.tbuf));
-  GatherArgs g{reinterpret_cast<double2*>(D.ws + L.state0), reinterpret_cast<double2*>(D.ws + L.state1), step,
-               (uint64_t(1) << step) - 1};
+  double2* s0 = reinterpret_cast<double2*>(D.ws + L.state0);
+  // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0
+  GatherArgs g{s0, dbl ? s0 + (int64_t(1) << step) * d : reinterpret_cast<double2*>(D.ws + L.state1), step,
+               dbl ? kDoubling : (uint64_t(1) << step) - 1};
   const int tiles_n = (d + 63) / 64;
   zgemm_tile<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
 }
@@ -387,8 +389,8 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
 }
 
 hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                              bool mixed, bool polar, hipStream_t s) {
-  const int m = mixed ? 1 : 0, p = polar ? 1 : 0;
+                              bool mixed, int bflags, hipStream_t s) {
+  const int m = mixed ? 1 : 0, p = bflags;
   switch (kind) {
     case BK_SQ:
       hipLaunchKernelGGL(kb_zgemm<BK_SQ>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
@@ -405,9 +407,9 @@ hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const in
   return hipGetLastError();
 }
 
-hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool polar,
+hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, int bflags,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(kb_ctrl_f64, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, polar ? 1 : 0);
+  hipLaunchKernelGGL(kb_ctrl_f64, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, bflags);
   return hipGetLastError();
 }
 

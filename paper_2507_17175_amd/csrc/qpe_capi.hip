@@ -64,12 +64,13 @@ struct BatchPlan {
 BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, bool with_report) {
   BatchPlan P;
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
+  const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
   int32_t table_ints = 0;
   auto add = [&](int kind, int step) {
     int members = 0;
     int64_t tiles = 0;
     for (int i = 0; i < count; ++i) {
-      int64_t w = batch_tiles(kind, step, p[i].n_meas, p[i].n_mat, mixed, polar);
+      int64_t w = batch_tiles(kind, step, p[i].n_meas, p[i].n_mat, mixed, polar, dbl);
       if (w > 0) {
         ++members;
         tiles += w;
@@ -148,7 +149,7 @@ qpe_status check_problem(const qpe_problem& p, bool need_ptrs) {
 
 qpe_status check_form_flags(int form, unsigned flags) {
   if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
-  if (flags & ~unsigned(QPE_NO_POLAR)) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING)) return QPE_ERR_ARG;
   return QPE_OK;
 }
 
@@ -296,10 +297,14 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + L.scratch);
   const double2* psi = static_cast<const double2*>(p.psi);
 
+  const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
+  const size_t amp = mixed ? 8 : 16;
   QPE_HIP(ctx, launch_zero_u64(defect, 1, s));
   {
+    // Prefix doubling writes every row j >= 1 in the step of its top bit,
+    // so the H layer only has to fill row 0.
     TimerScope ts(ctx, QPE_TIMER_HLAYER);
-    QPE_HIP(ctx, launch_h_broadcast(mixed, psi, s0, n, t, s));
+    QPE_HIP(ctx, launch_h_broadcast(mixed, psi, s0, n, t, s, dbl));
   }
   const double2* cur = static_cast<const double2*>(p.U);
   for (int k = 0; k < n; ++k) {
@@ -311,10 +316,18 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       if (st != QPE_OK) return st;
       cur = polar ? other : sq;
     }
-    qpe_status st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1);
+    qpe_status st;
+    if (dbl) {
+      // rows [0, 2^k) of s0 -> rows [2^k, 2^(k+1)) of s0: 2^k outputs, as a
+      // "register" of k+1 qubits whose second buffer starts at row 2^k.
+      char* upper = static_cast<char*>(s0) + (size_t(1) << k) * size_t(d) * amp;
+      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling);
+    } else {
+      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1);
+    }
     if (st != QPE_OK) return st;
   }
-  qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, true, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
+  qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, !dbl, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
                                  reinterpret_cast<double2*>(ws + L.tw_lo));
   if (st != QPE_OK) return st;
   if (report) QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, s));
@@ -341,6 +354,7 @@ int timer_of(int kind) {
 qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, unsigned flags, char* ws,
                      qpe_report* report) {
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
+  const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0);
   hipStream_t s = ctx->stream;
   const BatchPlan P = plan_batch(p, count, form, flags, true);
   int32_t* tables = reinterpret_cast<int32_t*>(ws);
@@ -359,7 +373,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
   const int nl = int(P.launches.size());
   for (int first = 0; first < nl; first += kBatchLaunchChunk) {
     int c = nl - first < kBatchLaunchChunk ? nl - first : kBatchLaunchChunk;
-    QPE_HIP(ctx, launch_batch_tables(desc, count, tables, P.launches.data() + first, c, mixed, polar, s));
+    QPE_HIP(ctx, launch_batch_tables(desc, count, tables, P.launches.data() + first, c, mixed, bf, s));
   }
   for (int l = 0; l < nl; ++l) {
     const BatchLaunch& L = P.launches[l];
@@ -370,24 +384,24 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_SQ:
       case BK_GRAM:
       case BK_CORR:
-        QPE_HIP(ctx, launch_batch_zgemm(L.kind, L.step, desc, tab, tiles, mixed, polar, s));
+        QPE_HIP(ctx, launch_batch_zgemm(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
         break;
       case BK_CTRL_SMALL:
-        QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, polar, s));
+        QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, bf, s));
         break;
       case BK_CTRL_M32:
       case BK_CTRL_M64:
       case BK_CTRL_M128:
-        QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, polar, s));
+        QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, bf, s));
         break;
       case BK_CTRL_F64:
-        QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, polar, s));
+        QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, bf, s));
         break;
       case BK_QFT:
-        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, polar, s));
+        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, bf, s));
         break;
       default:
-        QPE_HIP(ctx, launch_batch_elementwise(L.kind, L.step, desc, tab, tiles, mixed, polar, s));
+        QPE_HIP(ctx, launch_batch_elementwise(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
     }
   }
   return QPE_OK;
@@ -580,7 +594,7 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
                               void* workspace, size_t workspace_bytes, qpe_report* report) {
   if (!ctx || !U || !V_out) return QPE_ERR_ARG;
   if (n_mat < 0 || n_mat > QPE_MAX_N_MAT || count_k < 1 || count_k > QPE_MAX_N_MEAS) return QPE_ERR_SIZE;
-  if (flags & ~unsigned(QPE_NO_POLAR)) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING)) return QPE_ERR_ARG;
   if (misaligned(U, 16) || misaligned(V_out, 16) || (report && misaligned(report, 8))) return QPE_ERR_ALIGN;
   size_t need = 0;
   qpe_powers_workspace_size(n_mat, &need);

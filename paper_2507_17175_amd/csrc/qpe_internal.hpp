@@ -63,6 +63,22 @@ __host__ __device__ inline int row_parity(int64_t j, uint64_t pmask) {
   return __builtin_popcountll(uint64_t(j) & pmask) & 1;
 }
 
+// Prefix doubling: since the measurement register starts in |0...0>, the
+// rows [2^k, 2^(k+1)) of the state equal rows [0, 2^k) times V_k^T, so step k
+// can read rows i < 2^k of buf0 and write them to buf1 = buf0 + 2^k rows.
+// The controlled-step kernels take this mapping when the top bit of their
+// pmask argument is set (the gate route's masks 2^k - 1 never reach it).
+constexpr uint64_t kDoubling = uint64_t(1) << 63;
+
+// Row of the i-th output of a controlled step.
+__host__ __device__ inline int64_t step_row(int64_t i, int k, uint64_t pmask) {
+  return (pmask & kDoubling) ? i : ctrl_row(i, k);
+}
+// Buffer (0/1) that row j is read from; it is written to the other one.
+__host__ __device__ inline int src_buffer(int64_t j, uint64_t pmask) {
+  return (pmask & kDoubling) ? 0 : row_parity(j, pmask);
+}
+
 // ------------------------------------------------------ workspace layout
 
 constexpr size_t kAlign = 256;
@@ -158,13 +174,20 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 
 // Workgroups instance (n, t) contributes to launch (kind, step); 0 if it
 // takes no part. step = controlled step k, or the DFT pass index.
-__host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t, bool mixed, bool polar) {
-  const int64_t N = int64_t(1) << n, d = int64_t(1) << t, half = N / 2;
+// Flag bits of the grouped kernels' `bflags` argument.
+constexpr int kBatchPolar = 1, kBatchDoubling = 2;
+
+__host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t, bool mixed, bool polar,
+                                               bool dbl = false) {
+  const int64_t N = int64_t(1) << n, d = int64_t(1) << t;
+  // rows a controlled step writes: the gate route's N/2 rows with bit k set,
+  // or the 2^k new rows of the prefix-doubling form
+  const int64_t half = dbl ? (step < n ? (int64_t(1) << step) : 0) : N / 2;
   switch (kind) {
     case BK_ZERO:
       return 1;
     case BK_HLAYER:
-      return cdiv(N * d, kHTile);
+      return cdiv(dbl ? d : N * d, kHTile);
     case BK_TWIDDLE: {
       int h = tw_split(n);
       return cdiv((int64_t(1) << h) + (int64_t(1) << (n - h)), 256);
@@ -227,7 +250,8 @@ struct BatchLaunch {
 };
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s);
+hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s,
+                              bool first_row_only = false);
 hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s);
 hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s);
 hipError_t launch_sub_identity_defect(double2* G, int d, unsigned long long* defect_bits, hipStream_t s);
@@ -289,20 +313,20 @@ constexpr int kBatchLaunchChunk = 160;
 hipError_t launch_batch_descs(InstDesc* desc, char* ws, const BatchProblem* probs, int first, int count,
                               hipStream_t s);
 hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables, const BatchLaunch* launches,
-                               int nlaunch, bool mixed, bool polar, hipStream_t s);
+                               int nlaunch, bool mixed, int bflags, hipStream_t s);
 // Elementwise kinds (zero, H layer, twiddles, identity subtraction, split,
 // readout, report).
 hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                    bool mixed, bool polar, hipStream_t s);
+                                    bool mixed, int bflags, hipStream_t s);
 hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                              bool mixed, bool polar, hipStream_t s);
-hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool polar,
+                              bool mixed, int bflags, hipStream_t s);
+hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, int bflags,
                                  hipStream_t s);
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                   bool polar, hipStream_t s);
+                                   int bflags, hipStream_t s);
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                                   bool polar, hipStream_t s);
+                                   int bflags, hipStream_t s);
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                            bool polar, hipStream_t s);
+                            int bflags, hipStream_t s);
 
 }  // namespace qpe

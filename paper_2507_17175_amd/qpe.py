@@ -23,6 +23,7 @@ FORM_FP64 = 0
 FORM_MIXED = 1
 FORMS = {"fp64": FORM_FP64, "mixed": FORM_MIXED}
 NO_POLAR = 1
+PREFIX_DOUBLING = 2
 REPORT_NOT_UNITARY = 1
 REPORT_NUMERIC = 2
 
