@@ -404,30 +404,46 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 
 // Grouped controlled step k over the instances of a launch table; the tile
 // shape follows the operator size class of the launch (d = 32, 64, >= 128).
+// The BK_NS_* kinds run the Newton-Schulz correction X E of power step
+// `step` instead: X (complex64, in tbuf) rows [0, d) times the split planes of
+// E, written to gbuf, through the prefix-doubling mapping of a t+1 qubit
+// register.
 template <int KIND>
-__global__ void __launch_bounds__(KIND == BK_CTRL_M32 ? 256 : 512)
+__global__ void __launch_bounds__(KIND == BK_CTRL_M32 || KIND == BK_NS_M32 ? 256 : 512)
 kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags) {
+  constexpr bool NS = KIND == BK_NS_M32 || KIND == BK_NS_M64 || KIND == BK_NS_M128;
+  constexpr int BN = (KIND == BK_CTRL_M32 || KIND == BK_NS_M32) ? 32 : ((KIND == BK_CTRL_M64 || KIND == BK_NS_M64) ? 64 : 128);
   int64_t local;
   const int i = find_member(table, blockIdx.x, &local);
   const InstDesc D = desc[i];
-  const bool dbl = (bflags & kBatchDoubling) != 0;
+  const bool dbl = NS || (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, true, (bflags & kBatchPolar) != 0);
-  float2* s0 = reinterpret_cast<float2*>(D.ws + L.state0);
-  // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0, as a
-  // k+1 qubit register whose second buffer starts at row 2^k
-  float2* s1 = dbl ? s0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<float2*>(D.ws + L.state1);
   const uint16_t* planes = reinterpret_cast<const uint16_t*>(D.ws + L.planes);
+  float2* s0;
+  float2* s1;
+  int n, k;
+  if (NS) {
+    s0 = reinterpret_cast<float2*>(D.ws + L.tbuf);
+    s1 = reinterpret_cast<float2*>(D.ws + L.gbuf);
+    n = D.t + 1;
+    k = D.t;
+  } else {
+    s0 = reinterpret_cast<float2*>(D.ws + L.state0);
+    // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0, as a
+    // k+1 qubit register whose second buffer starts at row 2^k
+    s1 = dbl ? s0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<float2*>(D.ws + L.state1);
+    n = dbl ? step + 1 : D.n;
+    k = step;
+  }
   const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
-  const int n = dbl ? step + 1 : D.n;
-  constexpr int BN = KIND == BK_CTRL_M32 ? 32 : (KIND == BK_CTRL_M64 ? 64 : 128);
   const int tiles_n = (1 << D.t) / BN;
   const int tm = int(local / tiles_n), tn = int(local % tiles_n);
-  if constexpr (KIND == BK_CTRL_M32)
-    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
-  else if constexpr (KIND == BK_CTRL_M64)
-    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
+  if constexpr (BN == 32)
+    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+  else if constexpr (BN == 64)
+    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else
-    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, step, pmask, tm, tn);
+    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
 }
 
 template <int NT, typename K>
@@ -451,6 +467,11 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }
+  // Few rows (the Newton-Schulz correction X E, early prefix-doubling
+  // steps): 64 x 64 tiles keep four times as many CUs busy.
+  const int64_t big_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
+  if (t >= 6 && big_tiles < 256)
+    return launch<256>(k_ctrl_bf16x6<64, 64, 2, 2>, 64, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t >= 7) return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
@@ -469,6 +490,15 @@ hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, con
       break;
     case BK_CTRL_M128:
       hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M128>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
+      break;
+    case BK_NS_M32:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M32>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, p);
+      break;
+    case BK_NS_M64:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M64>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
+      break;
+    case BK_NS_M128:
+      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M128>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
       break;
     default:
       return hipErrorInvalidValue;

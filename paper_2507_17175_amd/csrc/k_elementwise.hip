@@ -87,11 +87,13 @@ __device__ inline uint16_t bf16_rne(double x, double* rounded) {
 // plane the layout is blocked by 16 columns: element (row j, col c) sits at
 // ((c / 16) * d + j) * 16 + c % 16, so that a tile of consecutive rows and 16
 // consecutive columns is contiguous.
-__device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e) {
+__device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e,
+                                   bool conj = false) {
   const int64_t d = int64_t(1) << t;
   const int64_t dd = d * d;
   int64_t j = e >> t, c = e & (d - 1);
   double2 v = V[e];
+  if (conj) v.y = -v.y;
   int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
   double w[2] = {v.x, v.y};
 #pragma unroll
@@ -229,6 +231,39 @@ __global__ void __launch_bounds__(kThreads) k_twiddles(double2* __restrict__ tw_
   int64_t total = (int64_t(1) << h) + (int64_t(1) << (n - h));
   for (int64_t t = blockIdx.x * int64_t(kThreads) + threadIdx.x; t < total; t += int64_t(gridDim.x) * kThreads)
     twiddle_entry(tw_hi, tw_lo, n, h, t);
+}
+
+// Newton-Schulz correction X E in split BF16 (E = X^H X - I is ~1e-15, so
+// X rounded to FP32 and E split into three BF16 pieces give X E to ~1e-22):
+// X32 = complex64(X), and planes = split(conj(E)) = split(E^T) (E is
+// Hermitian), so that the controlled-product kernel's row x V^T with
+// V = conj(E) computes row x E.
+__device__ inline void ns_prep_entry(const double2* __restrict__ X, const double2* __restrict__ E,
+                                     float2* __restrict__ X32, uint16_t* __restrict__ planes, int t, int64_t e) {
+  double2 x = X[e];
+  X32[e] = make_float2(float(x.x), float(x.y));
+  split_entry(E, planes, t, e, true);
+}
+
+// out = X - (X E) / 2 in FP64 (one Newton-Schulz step).
+__device__ inline void ns_update_entry(const double2* __restrict__ X, const float2* __restrict__ XE,
+                                       double2* __restrict__ out, int64_t e) {
+  double2 x = X[e];
+  float2 c = XE[e];
+  out[e] = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
+}
+
+__global__ void __launch_bounds__(kThreads) k_ns_prep(const double2* __restrict__ X, const double2* __restrict__ E,
+                                                      float2* __restrict__ X32, uint16_t* __restrict__ planes, int t) {
+  const int64_t dd = int64_t(1) << (2 * t);
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
+    ns_prep_entry(X, E, X32, planes, t, e);
+}
+
+__global__ void __launch_bounds__(kThreads) k_ns_update(const double2* __restrict__ X, const float2* __restrict__ XE,
+                                                        double2* __restrict__ out, int64_t dd) {
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
+    ns_update_entry(X, XE, out, e);
 }
 
 __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
@@ -384,6 +419,23 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       subi_range(reinterpret_cast<double2*>(D.ws + L.gbuf), d, e0 + threadIdx.x, e1, kThreads, defect);
       break;
     }
+    case BK_NSPREP:
+    case BK_NSUPD: {
+      // X = vbuf, E (then XE) = gbuf, X32 (then V_k) = tbuf
+      const double2* X = reinterpret_cast<const double2*>(D.ws + L.vbuf);
+      int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
+      if (kind == BK_NSPREP) {
+        const double2* E = reinterpret_cast<const double2*>(D.ws + L.gbuf);
+        float2* x32 = reinterpret_cast<float2*>(D.ws + L.tbuf);
+        uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) ns_prep_entry(X, E, x32, planes, t, e);
+      } else {
+        const float2* xe = reinterpret_cast<const float2*>(D.ws + L.gbuf);
+        double2* out = reinterpret_cast<double2*>(D.ws + L.tbuf);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) ns_update_entry(X, xe, out, e);
+      }
+      break;
+    }
     case BK_SPLIT: {
       const double2* V = power_ptr(D, L, power_slot(step, polar));
       uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
@@ -434,6 +486,18 @@ hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, i
 hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s) {
   int64_t work = (int64_t(1) << h) + (int64_t(1) << (n - h));
   hipLaunchKernelGGL(k_twiddles, dim3(grid_for(work)), dim3(kThreads), 0, s, tw_hi, tw_lo, n, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_prep(const double2* X, const double2* E, float2* X32, uint16_t* planes, int t, hipStream_t s) {
+  int64_t dd = int64_t(1) << (2 * t);
+  hipLaunchKernelGGL(k_ns_prep, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, E, X32, planes, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_update(const double2* X, const float2* XE, double2* out, int t, hipStream_t s) {
+  int64_t dd = int64_t(1) << (2 * t);
+  hipLaunchKernelGGL(k_ns_update, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, dd);
   return hipGetLastError();
 }
 

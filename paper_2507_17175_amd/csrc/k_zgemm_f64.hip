@@ -234,14 +234,28 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
             o.y += a.beta.x * c.y + a.beta.y * c.x;
           }
           a.C[int64_t(gi) * a.ldc + gj] = o;
+          // Hermitian product: only tiles on or above the diagonal run, and
+          // the ones above it also fill their mirror image.
+          if (a.herm && tile_n > tile_m) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
         }
       }
+}
+
+// Tile (row, column) of workgroup w among the T (T + 1) / 2 tiles on or above
+// the diagonal of a T x T tile grid, row by row.
+__device__ inline int2 upper_tile(int w, int T) {
+  int tm = 0;
+  while (w >= T - tm) {
+    w -= T - tm;
+    ++tm;
+  }
+  return make_int2(tm, tm + w);
 }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
   const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
-  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  const int2 tile = a.herm ? upper_tile(blockIdx.x, tiles_m) : xcd_tile(tiles_m, tiles_n);
   zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN>(a, g, tile.x, tile.y);
 }
 
@@ -287,7 +301,13 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
     a.C = tbuf;
   }
   GatherArgs g{};
-  zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+  if (KIND == BK_GRAM) {
+    a.herm = 1;
+    const int2 tile = upper_tile(int(local), tiles_n);
+    zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, tile.x, tile.y);
+  } else {
+    zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+  }
 }
 
 // FP64-form controlled step k with 64 x 64 tiles.
@@ -314,8 +334,12 @@ __global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __r
 }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
-hipError_t go(const ZgemmArgs& a, const GatherArgs& g, hipStream_t s) {
-  int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+hipError_t go(const ZgemmArgs& a_in, const GatherArgs& g, hipStream_t s) {
+  ZgemmArgs a = a_in;
+  // the Hermitian shortcut needs square tiles on a square product
+  if (a.herm && (BM != BN || a.M != a.N)) a.herm = 0;
+  const int T = (a.M + BM - 1) / BM;
+  int tiles = a.herm ? T * (T + 1) / 2 : T * ((a.N + BN - 1) / BN);
   hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
   return hipGetLastError();
 }
@@ -330,8 +354,13 @@ hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
     // Default (measured on MI355X): 64x64 tiles with 8 waves once there
     // are >= 128 of them (d >= 1024: 7.2 ms per 15 squaring steps vs 7.9 ms
     // for 32x32), 32x32 tiles below (d = 256: 1.34 ms vs 2.5 ms).
-    int64_t tiles64 = int64_t((a.M + 63) / 64) * ((a.N + 63) / 64);
-    variant = tiles64 >= 128 ? 3 : 1;
+    // A Hermitian product runs only the tiles on or above the diagonal, so
+    // it needs a larger grid before 64x64 tiles fill the chip.
+    const int64_t t64 = (a.M + 63) / 64;
+    if (a.herm && a.M == a.N)
+      variant = t64 * (t64 + 1) / 2 >= 256 ? 3 : 1;
+    else
+      variant = t64 * ((a.N + 63) / 64) >= 128 ? 3 : 1;
   }
   switch (variant) {
     case 1: return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);

@@ -98,6 +98,11 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
         add(BK_GRAM, k);
         add(BK_SUBI, k);
         add(BK_CORR, k);
+        add(BK_NSPREP, k);
+        add(BK_NS_M32, k);
+        add(BK_NS_M64, k);
+        add(BK_NS_M128, k);
+        add(BK_NSUPD, k);
       }
     }
     if (mixed) {
@@ -209,8 +214,13 @@ struct TimerScope {
 //   X <- X (3I - X^H X) / 2 = X - X (X^H X - I) / 2,
 // whose E = X^H X - I also yields the unitarity defect max|E_ij|.
 // sq and out are distinct from cur; out may equal the dead predecessor.
+// With planes (the mixed form, d >= 32) the correction X E runs on the
+// split-BF16 controlled-product kernel: X rounded to complex64 (staged in
+// out) times E split into three BF16 pieces (E is O(defect), so the
+// product's error is O(1e-7 defect), far below the FP64 rounding of X),
+// accumulated in FP32 into g, which E no longer needs by then.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
-                            bool polar, unsigned long long* defect) {
+                            bool polar, unsigned long long* defect, uint16_t* planes = nullptr) {
   hipStream_t s = ctx->stream;
   const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
@@ -229,8 +239,20 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   h.A = sq;
   h.B = sq;
   h.C = g;
+  h.herm = 1;
   QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // G = X^H X
   QPE_HIP(ctx, launch_sub_identity_defect(g, d, defect, s));
+  if (planes && tz >= 5) {
+    float2* x32 = reinterpret_cast<float2*>(out);
+    float2* xe = reinterpret_cast<float2*>(g);
+    QPE_HIP(ctx, launch_ns_prep(sq, g, x32, planes, tz, s));
+    // Prefix-doubling mapping with a (t+1)-qubit register: rows [0, d) of
+    // x32 times E land in rows [0, d) of xe.
+    QPE_HIP(ctx, launch_ctrl_mixed(x32, xe, planes, tz + 1, tz, tz, kDoubling, s,
+                                   ctx->variant[QPE_KERNEL_CTRL_MIXED][tz]));
+    QPE_HIP(ctx, launch_ns_update(sq, xe, out, tz, s));
+    return QPE_OK;
+  }
   ZgemmArgs c = a;
   c.A = sq;
   c.B = g;
@@ -312,7 +334,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes);
       if (st != QPE_OK) return st;
       cur = polar ? other : sq;
     }
@@ -341,7 +363,9 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
 int timer_of(int kind) {
   switch (kind) {
     case BK_HLAYER: return QPE_TIMER_HLAYER;
-    case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR: return QPE_TIMER_POWERS;
+    case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR:
+    case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD:
+      return QPE_TIMER_POWERS;
     case BK_SPLIT: return QPE_TIMER_SPLIT;
     case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_F64:
       return QPE_TIMER_CTRL_GEMM;
@@ -392,6 +416,9 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_CTRL_M32:
       case BK_CTRL_M64:
       case BK_CTRL_M128:
+      case BK_NS_M32:
+      case BK_NS_M64:
+      case BK_NS_M128:
         QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, bf, s));
         break;
       case BK_CTRL_F64:

@@ -144,6 +144,11 @@ enum BatchKind {
   BK_GRAM,
   BK_SUBI,
   BK_CORR,
+  BK_NSPREP,   // split-BF16 Newton-Schulz correction (mixed form, d >= 32):
+  BK_NS_M32,   //   prep, X E on the controlled-product kernel (by size
+  BK_NS_M64,   //   class), update
+  BK_NS_M128,
+  BK_NSUPD,
   BK_SPLIT,
   BK_CTRL_SMALL,
   BK_CTRL_M32,
@@ -194,9 +199,23 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     }
     case BK_SQ:
       return (step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
-    case BK_GRAM:
+    case BK_GRAM: {
+      // Hermitian: the tiles on or above the diagonal
+      const int64_t T = cdiv(d, kBatchGemmTile);
+      return (polar && step >= 1 && step < n) ? T * (T + 1) / 2 : 0;
+    }
     case BK_CORR:
-      return (polar && step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
+      return (polar && !(mixed && t >= 5) && step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile)
+                                                                     : 0;
+    case BK_NSPREP:
+    case BK_NSUPD:
+      return (polar && mixed && t >= 5 && step >= 1 && step < n) ? cdiv(d * d, kSplitTile) : 0;
+    case BK_NS_M32:
+      return (polar && mixed && t == 5 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 32) : 0;
+    case BK_NS_M64:
+      return (polar && mixed && t == 6 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 64) : 0;
+    case BK_NS_M128:
+      return (polar && mixed && t >= 7 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 128) : 0;
     case BK_SUBI:
       return (polar && step >= 1 && step < n) ? cdiv(d * d, kSubiTile) : 0;
     case BK_SPLIT:
@@ -254,6 +273,10 @@ hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, i
                               bool first_row_only = false);
 hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s);
 hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s);
+// Newton-Schulz correction in split BF16: X32 = complex64(X), planes =
+// split(conj(E)); then out = X - XE / 2 (XE = X32 E from the mixed kernel).
+hipError_t launch_ns_prep(const double2* X, const double2* E, float2* X32, uint16_t* planes, int t, hipStream_t s);
+hipError_t launch_ns_update(const double2* X, const float2* XE, double2* out, int t, hipStream_t s);
 hipError_t launch_sub_identity_defect(double2* G, int d, unsigned long long* defect_bits, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
@@ -275,6 +298,9 @@ struct ZgemmArgs {
   long ldcin;
   double2* C;
   long ldc;
+  // Hermitian result (op(A) = B^H, alpha real, beta 0): only tiles on or
+  // above the diagonal are computed; each mirrors itself below it.
+  int herm;
 };
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant);
 int zgemm_variants();
