@@ -88,6 +88,31 @@ __device__ __forceinline__ void mma_bf16x6(f32x16 (&acc_re)[FM][FN], f32x16 (&ac
   }
 }
 
+// The four MFMA products of piece pair c alone (c = 0..5 in the order of
+// mma_bf16x6), so that other work can be placed between the pairs.
+template <int FM, int FN>
+__device__ __forceinline__ void mma_pair(int c, f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
+                                         const bf16x8 (&av)[FM][6], const bf16x8 (&bv)[FN][6],
+                                         const bf16x8 (&bneg)[FN][3]) {
+  constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
+  constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
+  const int pa = PA[c], pb = PB[c];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+      acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb], acc_re[x][y], 0, 0, 0);
+      acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa], bv[y][2 * pb + 1], acc_im[x][y], 0, 0, 0);
+    }
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+      acc_re[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bneg[y][pb], acc_re[x][y], 0, 0, 0);
+      acc_im[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[x][2 * pa + 1], bv[y][2 * pb], acc_im[x][y], 0, 0, 0);
+    }
+}
+
 // Output layout of the 32x32 MFMA: lane l, element v holds row
 // 8 * (v / 4) + 4 * (l / 32) + v % 4, column l % 32 of the block.
 template <int FM, int FN>
@@ -108,7 +133,7 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const
 }
 
 // ----------------------------------------------------------------- variant 2
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool IL = true>
 __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                              const uint16_t* __restrict__ planes, int n, int t, int k,
                                              uint64_t pmask, int tile_m, int tile_n) {
@@ -167,31 +192,37 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
     }
   };
 
-  auto store_lds = [&](int b) {
+  // The split of the prefetched A slab, one complex column u (0..3) of each
+  // thread's 4-complex chunk at a time, into pieces pc (re/im x hi/mid/lo).
+  bf16x4 pc[CA][6];
+  auto split_part = [&](int u) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4 w = ra[q][u >> 1];
+      __bf16 h, m, l;
+      split3((u & 1) ? w.z : w.x, h, m, l);  // real part
+      pc[q][0][u] = h;
+      pc[q][2][u] = m;
+      pc[q][4][u] = l;
+      split3((u & 1) ? w.w : w.y, h, m, l);  // imaginary part
+      pc[q][1][u] = h;
+      pc[q][3][u] = m;
+      pc[q][5][u] = l;
+    }
+  };
+  auto write_a = [&](int b) {
     uint16_t* base = lds + b * BUF;
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
       int c = tid + q * NT;
       int r = c / 4, kq = c & 3;
-      float v[8] = {ra[q][0].x, ra[q][0].y, ra[q][0].z, ra[q][0].w,
-                    ra[q][1].x, ra[q][1].y, ra[q][1].z, ra[q][1].w};
-      bf16x4 pc[6];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        __bf16 h, m, l;
-        split3(v[2 * u], h, m, l);  // real part
-        pc[0][u] = h;
-        pc[2][u] = m;
-        pc[4][u] = l;
-        split3(v[2 * u + 1], h, m, l);  // imaginary part
-        pc[1][u] = h;
-        pc[3][u] = m;
-        pc[5][u] = l;
-      }
 #pragma unroll
       for (int pl = 0; pl < 6; ++pl)
-        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[pl];
+        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
     }
+  };
+  auto write_b = [&](int b) {
+    uint16_t* base = lds + b * BUF;
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
       int idx = tid + q * NT;
@@ -199,6 +230,12 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       int pl = idx / (BN * 2), w = idx % (BN * 2);
       *reinterpret_cast<u32x4*>(base + 6 * A_PLANE + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
     }
+  };
+  auto store_lds = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_part(u);
+    write_a(b);
+    write_b(b);
   };
 
   f32x16 acc_re[FM][FN], acc_im[FM][FN];
@@ -236,22 +273,43 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
 #pragma unroll
       for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
     }
-    mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
-    if (s + 1 < nk) store_lds((s + 1) & 1);
-    if (s + 2 < nk) load_global(s + 2);
+    // The store of slab s+1 and the loads of slab s+2 are unconditional: the
+    // last iteration writes the idle buffer (read in slab nk-2, which every
+    // wave has left) and the last two reload slab nk-1.
+    const int nb = (s + 1) & 1, ns = min(s + 2, nk - 1);
+    if (IL) {
+      // Explicit issue order: after each piece pair's MFMAs, a share of the
+      // next slab's split, LDS stores and global loads. In-order issue then
+      // runs that vector work while the matrix cores are still busy,
+      // instead of after the last MFMA of the slab.
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+        __builtin_amdgcn_sched_barrier(0);
+        if (c < 4) split_part(c);
+        if (c == 3) write_a(nb);
+        if (c == 4) write_b(nb);
+        if (c == 5) load_global(ns);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+      store_lds(nb);
+      load_global(ns);
+    }
     __syncthreads();
   }
 
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool IL = true>
 __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                          const uint16_t* __restrict__ planes, int n, int t, int k,
                                                          uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_db_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_db_tile<BM, BN, WM, WN, IL>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
 // ----------------------------------------------------------------- variant 1
@@ -457,13 +515,22 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 2; }
+int ctrl_mixed_variants() { return 3; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant) {
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (variant == 3) {
+    // the double-buffered kernel with the compiler's own issue order
+    if (t >= 7)
+      return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4, false>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6)
+      return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2, false>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }
