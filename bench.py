@@ -127,6 +127,11 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--study", choices=["precision"], default=None,
+                    help="precision: the estimator study (section 4.2) over every eigenvector of a 16 x 16 Haar "
+                         "unitary for n = --study-n-min .. --study-n-max; prints one JSON line and exits")
+    ap.add_argument("--study-n-min", type=int, default=4)
+    ap.add_argument("--study-n-max", type=int, default=24)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates the HBM byte "
                          "counters of a profiler pass) and exit")
@@ -143,6 +148,33 @@ def copy_probe(mib: int) -> int:
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_per_launch": n, "launches": 3}), flush=True)
+    return 0
+
+
+def precision_study_main(a) -> int:
+    """Estimator errors against the exact eigenphases, per n and form."""
+    import torch
+    from paper_2507_17175_amd import qpe, study
+    from workloads import eigenbasis_problems
+
+    qpe.load_library()
+    probs = eigenbasis_problems(a.study_n_min, n_mat=4, seed=12)
+    U = torch.from_numpy(probs[0].U).cuda()
+    psis = [torch.from_numpy(p.psi).cuda() for p in probs]
+    ns = list(range(a.study_n_min, a.study_n_max + 1))
+    out = {"study": "phase-estimator precision vs N_meas (section 4.2)",
+           "workload": "every eigenvector of one seeded 16 x 16 Haar unitary (uniform eigenphases), 16 instances "
+                       "per n, batched",
+           "estimators": {"argmax": "max-norm: argmax_m P(m) / N", "weighted": "sum_m P(m) m / N (plain |error|)",
+                          "circular": "arg(sum_m P(m) exp(2 pi i m / N)) / 2 pi (circular error)"}}
+    for form in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        rows = study.precision_study(U, psis, probs[0].phis, ns, form=form)
+        torch.cuda.synchronize()
+        out[form] = {"rows": rows, "seconds": round(time.perf_counter() - t0, 3),
+                     "log2_slope_argmax": round(study.halving_slope(rows, "argmax_mean"), 3),
+                     "log2_slope_circular": round(study.halving_slope(rows, "circular_mean"), 3)}
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -173,6 +205,8 @@ def main():
         return 2
     if a.copy_probe_mib:
         return copy_probe(a.copy_probe_mib)
+    if a.study == "precision":
+        return precision_study_main(a)
     import torch
     from paper_2507_17175_amd import qpe
     from workloads import config_problems

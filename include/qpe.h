@@ -182,6 +182,37 @@ qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size_t *byte
 qpe_status qpe_iqft_probs(qpe_ctx *ctx, int n_meas, int n_mat, int form, void *state,
                           double *prob, void *workspace, size_t workspace_bytes);
 
+/* ---- phase estimators (paper section 4.2, precision evaluation) ----
+ * From each problem's probability vector P = problems[i].prob (device
+ * float64 [N], N = 2^n_meas, as written by qpe_run; only n_meas and prob are
+ * read), out[i] receives
+ *   argmax_index   : the m with the largest P(m), the smallest such m on a
+ *                    tie; NaN entries are never chosen (-1 if all are NaN);
+ *   argmax_phase   : argmax_index / N, the max-norm estimator (NaN if -1);
+ *   weighted_phase : sum_m P(m) (m / N) / sum_m P(m), the weighted-average
+ *                    estimator as the paper states it (biased for phases
+ *                    near the 0/1 wrap);
+ *   circular_phase : arg(sum_m P(m) exp(2 pi i m / N)) / (2 pi) in [0, 1),
+ *                    the circular mean (no bias at the wrap);
+ *   prob_sum       : sum_m P(m).
+ * Sums run in FP64 over a partition of m that depends only on N, so the
+ * results are reproducible. problems: HOST array; out: DEVICE array of
+ * `count` qpe_estimates, 8-byte aligned; workspace: device, 256-aligned,
+ * >= qpe_estimate_workspace_size(count). Asynchronous on the context stream.
+ * Errors: QPE_ERR_ARG, QPE_ERR_SIZE, QPE_ERR_ALIGN, QPE_ERR_WORKSPACE,
+ * QPE_ERR_HIP. */
+typedef struct qpe_estimates {
+  double argmax_phase;
+  double weighted_phase;
+  double circular_phase;
+  double prob_sum;
+  int64_t argmax_index;
+  int64_t reserved;
+} qpe_estimates;
+qpe_status qpe_estimate_workspace_size(int count, size_t *bytes);
+qpe_status qpe_estimate(qpe_ctx *ctx, const qpe_problem *problems, int count,
+                        qpe_estimates *out, void *workspace, size_t workspace_bytes);
+
 /* Complex FP64 GEMM on the matrix cores (the building block of the powers):
  * C = alpha * op(A) * op(B) + beta * Cin, op in {'N','T','C'} (none,
  * transpose, conjugate transpose); op(A) is M x K, op(B) is K x N; all

@@ -57,6 +57,7 @@ __all__ = [
     "superposition_probs",
     "estimate_argmax",
     "estimate_weighted",
+    "estimate_circular",
     "phase_error",
 ]
 
@@ -244,6 +245,17 @@ def estimate_weighted(P: np.ndarray) -> float:
     N = P.shape[0]
     m = np.arange(N, dtype=np.float64) / float(N)
     return float((P * m).sum() / P.sum())
+
+
+def estimate_circular(P: np.ndarray) -> float:
+    """Circular mean of the outcome phases m / 2^n weighted by P: the angle
+    of sum_m P(m) exp(2 pi i m / 2^n), divided by 2 pi, in [0, 1). Unlike
+    the plain weighted average it has no bias at the 0/1 wrap of phases."""
+    N = P.shape[0]
+    ang = 2.0 * np.pi * np.arange(N, dtype=np.float64) / float(N)
+    z = complex((P * np.cos(ang)).sum(), (P * np.sin(ang)).sum())
+    a = math.atan2(z.imag, z.real) / (2.0 * math.pi)
+    return a + 1.0 if a < 0.0 else a
 
 
 def phase_error(est: float, ref: float, circular: bool = True) -> float:

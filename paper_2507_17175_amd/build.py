@@ -29,6 +29,7 @@ SOURCES = [
     "k_ctrl_mixed.hip",
     "k_ctrl_small.hip",
     "k_qft.hip",
+    "k_estimate.hip",
 ]
 
 ARCH = "gfx950"

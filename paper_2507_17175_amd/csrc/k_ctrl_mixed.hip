@@ -468,11 +468,12 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 // register.
 template <int KIND>
 __global__ void __launch_bounds__(KIND == BK_CTRL_M32 || KIND == BK_NS_M32 ? 256 : 512)
-kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags) {
+kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags,
+              int64_t tile0) {
   constexpr bool NS = KIND == BK_NS_M32 || KIND == BK_NS_M64 || KIND == BK_NS_M128;
   constexpr int BN = (KIND == BK_CTRL_M32 || KIND == BK_NS_M32) ? 32 : ((KIND == BK_CTRL_M64 || KIND == BK_NS_M64) ? 64 : 128);
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const bool dbl = NS || (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, true, (bflags & kBatchPolar) != 0);
@@ -550,23 +551,29 @@ hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, con
   const int p = bflags;
   switch (kind) {
     case BK_CTRL_M32:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M32>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M32>, dim3(g), dim3(256), 0, s, step, desc, table, p, b);
+      });
     case BK_CTRL_M64:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M64>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M64>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
+      });
     case BK_CTRL_M128:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M128>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M128>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
+      });
     case BK_NS_M32:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M32>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M32>, dim3(g), dim3(256), 0, s, step, desc, table, p, b);
+      });
     case BK_NS_M64:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M64>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M64>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
+      });
     case BK_NS_M128:
-      hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M128>, dim3(unsigned(tiles)), dim3(512), 0, s, step, desc, table, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_ctrl_mixed<BK_NS_M128>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
+      });
     default:
       return hipErrorInvalidValue;
   }

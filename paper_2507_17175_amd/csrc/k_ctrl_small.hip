@@ -74,10 +74,11 @@ __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T
 // 256 gathered rows per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDesc* __restrict__ desc,
-                                                          const int32_t* __restrict__ table, int bflags) {
+                                                          const int32_t* __restrict__ table, int bflags,
+                                                          int64_t tile0) {
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed, pol);
@@ -130,13 +131,12 @@ hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* 
 
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
                                    int bflags, hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL(kb_ctrl_small<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
-                       bflags);
-  else
-    hipLaunchKernelGGL(kb_ctrl_small<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, step, desc, table,
-                       bflags);
-  return hipGetLastError();
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    if (mixed)
+      hipLaunchKernelGGL(kb_ctrl_small<float2>, dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+    else
+      hipLaunchKernelGGL(kb_ctrl_small<double2>, dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+  });
 }
 
 }  // namespace qpe

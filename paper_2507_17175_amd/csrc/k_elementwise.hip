@@ -381,11 +381,12 @@ __device__ inline const double2* power_ptr(const InstDesc& D, const RunLayout& L
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, const InstDesc* __restrict__ desc,
-                                                           const int32_t* __restrict__ table, int bflags) {
+                                                           const int32_t* __restrict__ table, int bflags,
+                                                           int64_t tile0) {
   const bool polar = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const RunLayout L = run_layout(D.n, D.t, mixed, polar);
   const int n = D.n, t = D.t, d = 1 << t;
@@ -575,13 +576,12 @@ hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables,
 
 hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                                     bool mixed, int bflags, hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL(kb_elementwise<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
-                       bflags);
-  else
-    hipLaunchKernelGGL(kb_elementwise<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, kind, step, desc, table,
-                       bflags);
-  return hipGetLastError();
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    if (mixed)
+      hipLaunchKernelGGL(kb_elementwise<float2>, dim3(g), dim3(kThreads), 0, s, kind, step, desc, table, bflags, b);
+    else
+      hipLaunchKernelGGL(kb_elementwise<double2>, dim3(g), dim3(kThreads), 0, s, kind, step, desc, table, bflags, b);
+  });
 }
 
 }  // namespace qpe

@@ -222,11 +222,11 @@ __global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, con
 // per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __restrict__ desc,
-                                                   const int32_t* __restrict__ table, int bflags) {
+                                                   const int32_t* __restrict__ table, int bflags, int64_t tile0) {
   constexpr bool mixed = sizeof(T) == 8;
   __shared__ T L[kQftLds];
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const RunLayout lay = run_layout(D.n, D.t, mixed, (bflags & kBatchPolar) != 0);
   const DftPlan plan = make_dft_plan(D.n);
@@ -282,11 +282,12 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
 
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
                             int bflags, hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL(kb_qft<float2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, bflags);
-  else
-    hipLaunchKernelGGL(kb_qft<double2>, dim3(unsigned(tiles)), dim3(kThreads), 0, s, pass, desc, table, bflags);
-  return hipGetLastError();
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    if (mixed)
+      hipLaunchKernelGGL(kb_qft<float2>, dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+    else
+      hipLaunchKernelGGL(kb_qft<double2>, dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+  });
 }
 
 hipError_t launch_qft_pass(bool mixed, void* buf0, const void* buf1, bool gather, int n, int t, int pass_bits,

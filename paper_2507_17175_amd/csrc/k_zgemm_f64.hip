@@ -266,11 +266,12 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
 // BK_CORR  V_k = X - X (G - I) / 2.
 template <int KIND>
 __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __restrict__ desc,
-                                                const int32_t* __restrict__ table, int mixed, int bflags) {
+                                                const int32_t* __restrict__ table, int mixed, int bflags,
+                                                int64_t tile0) {
   constexpr int T = kBatchGemmTile;
   constexpr int OPA = KIND == BK_GRAM ? OP_C : OP_N;
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const bool pol = (bflags & kBatchPolar) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed != 0, pol);
@@ -312,9 +313,9 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
 
 // FP64-form controlled step k with 64 x 64 tiles.
 __global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __restrict__ desc,
-                                                   const int32_t* __restrict__ table, int bflags) {
+                                                   const int32_t* __restrict__ table, int bflags, int64_t tile0) {
   int64_t local;
-  const int i = find_member(table, blockIdx.x, &local);
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
   const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, false, pol);
@@ -422,14 +423,17 @@ hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const in
   const int m = mixed ? 1 : 0, p = bflags;
   switch (kind) {
     case BK_SQ:
-      hipLaunchKernelGGL(kb_zgemm<BK_SQ>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_zgemm<BK_SQ>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
+      });
     case BK_GRAM:
-      hipLaunchKernelGGL(kb_zgemm<BK_GRAM>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_zgemm<BK_GRAM>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
+      });
     case BK_CORR:
-      hipLaunchKernelGGL(kb_zgemm<BK_CORR>, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, m, p);
-      break;
+      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+        hipLaunchKernelGGL(kb_zgemm<BK_CORR>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
+      });
     default:
       return hipErrorInvalidValue;
   }
@@ -438,8 +442,9 @@ hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const in
 
 hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, int bflags,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(kb_ctrl_f64, dim3(unsigned(tiles)), dim3(256), 0, s, step, desc, table, bflags);
-  return hipGetLastError();
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    hipLaunchKernelGGL(kb_ctrl_f64, dim3(g), dim3(256), 0, s, step, desc, table, bflags, b);
+  });
 }
 
 }  // namespace qpe

@@ -718,6 +718,37 @@ QPE_API qpe_status qpe_iqft_probs(qpe_ctx* ctx, int n_meas, int n_mat, int form,
   return iqft_and_probs(ctx, form == QPE_FORM_MIXED, n_meas, n_mat, state, nullptr, false, prob, tw_hi, tw_lo);
 }
 
+// ------------------------------------------------------------- estimators
+
+QPE_API qpe_status qpe_estimate_workspace_size(int count, size_t* bytes) {
+  if (!bytes || count < 1) return QPE_ERR_ARG;
+  *bytes = size_t(count) * est_workspace_bytes();
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_estimate(qpe_ctx* ctx, const qpe_problem* problems, int count, qpe_estimates* out,
+                                void* workspace, size_t workspace_bytes) {
+  if (!ctx || !problems || !out || count < 1) return QPE_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!problems[i].prob) return QPE_ERR_ARG;
+    if (problems[i].n_meas < 1 || problems[i].n_meas > QPE_MAX_N_MEAS) return QPE_ERR_SIZE;
+    if (misaligned(problems[i].prob, 8)) return QPE_ERR_ALIGN;
+  }
+  if (misaligned(out, 8)) return QPE_ERR_ALIGN;
+  size_t need = 0;
+  qpe_estimate_workspace_size(count, &need);
+  qpe_status s = check_workspace(workspace, workspace_bytes, need);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  char* ws = static_cast<char*>(workspace);
+  for (int i = 0; i < count; ++i)
+    QPE_HIP(ctx, launch_estimate(problems[i].prob, problems[i].n_meas, ws + size_t(i) * est_workspace_bytes(),
+                                 reinterpret_cast<double*>(out + i), ctx->stream));
+  return QPE_OK;
+}
+
 QPE_API qpe_status qpe_zgemm(qpe_ctx* ctx, char opA, char opB, int M, int N, int K, const double* alpha,
                              const void* A, int lda, const void* B, int ldb, const double* beta, const void* Cin,
                              int ldcin, void* C, int ldc) {

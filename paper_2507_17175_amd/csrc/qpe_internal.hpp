@@ -264,6 +264,22 @@ __device__ inline int find_member(const int32_t* __restrict__ tab, int64_t tile,
   return mem[lo];
 }
 
+// A grouped launch of more workgroups than this is split into several
+// launches over consecutive tile ranges (argument tile0 of the grouped
+// kernels), which keeps every grid far below the 2^32 work-item limit.
+constexpr int64_t kMaxGridBlocks = int64_t(1) << 22;
+
+template <typename F>
+hipError_t for_grid_chunks(int64_t tiles, F&& launch_one) {
+  for (int64_t base = 0; base < tiles; base += kMaxGridBlocks) {
+    const int64_t g = tiles - base < kMaxGridBlocks ? tiles - base : kMaxGridBlocks;
+    launch_one(unsigned(g), base);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 struct BatchLaunch {
   int32_t kind, step, table_off;  // table_off in int32 units
 };
@@ -285,6 +301,13 @@ hipError_t launch_report(const double* prob, int n, const double2* psi, int t,
                          const unsigned long long* defect_bits, void* report, hipStream_t s);
 hipError_t launch_copy_rows_back(bool mixed, void* state, const void* other, int n, int t, int k,
                                  hipStream_t s);
+
+// Phase estimators of one probability vector (k_estimate.hip): writes the
+// six 8-byte fields of qpe_estimates to out. scratch: est_workspace_bytes().
+constexpr int kEstMaxBlocks = 1024;
+int est_blocks(int n);
+size_t est_workspace_bytes();
+hipError_t launch_estimate(const double* P, int n, void* scratch, double* out, hipStream_t s);
 
 // C = alpha op(A) op(B) + beta Cin, complex FP64. op: 0 = N, 1 = T, 2 = C.
 struct ZgemmArgs {

@@ -39,7 +39,7 @@ EXPORTS = (
     "qpe_controlled_step", "qpe_iqft_workspace_size", "qpe_iqft_probs", "qpe_zgemm",
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
-    "qpe_kernel_variants", "qpe_ctx_set_variant",
+    "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
 )
 
 KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2}
@@ -64,6 +64,10 @@ class Problem(ctypes.Structure):
 REPORT_DTYPE = np.dtype([("unitarity_defect", "<f8"), ("prob_sum", "<f8"), ("psi_norm2", "<f8"),
                          ("flags", "<u4"), ("reserved", "<u4")])
 REPORT_BYTES = 32
+
+ESTIMATES_DTYPE = np.dtype([("argmax_phase", "<f8"), ("weighted_phase", "<f8"), ("circular_phase", "<f8"),
+                            ("prob_sum", "<f8"), ("argmax_index", "<i8"), ("reserved", "<i8")])
+ESTIMATES_BYTES = 48
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -102,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_kernel_variants": (st, [i32, ctypes.POINTER(i32)]),
             "qpe_ctx_set_variant": (st, [vp, i32, i32, i32]),
             "qpe_ctx_read_timing": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+            "qpe_estimate_workspace_size": (st, [i32, ctypes.POINTER(sz)]),
+            "qpe_estimate": (st, [vp, ctypes.POINTER(Problem), i32, vp, vp, sz]),
             "qpe_status_string": (ctypes.c_char_p, [i32]),
             "qpe_last_error": (ctypes.c_char_p, [vp]),
             "qpe_version": (ctypes.c_char_p, []),
@@ -260,6 +266,32 @@ def run(U: torch.Tensor, psi: torch.Tensor, n_meas: int, form="mixed", flags: in
     if report:
         return out[0][0], out[1][0]
     return out[0]
+
+
+def estimate(probs: Sequence[torch.Tensor]) -> np.ndarray:
+    """Phase estimators (max-norm, weighted average, circular mean) of each
+    float64 probability vector, computed on the device. Returns a numpy
+    structured array with ESTIMATES_DTYPE fields, one entry per vector."""
+    if not probs:
+        return np.zeros(0, dtype=ESTIMATES_DTYPE)
+    dev = _dev_index(probs[0])
+    arr = (Problem * len(probs))()
+    for i, p in enumerate(probs):
+        N = p.numel()
+        n = N.bit_length() - 1
+        if N != (1 << n) or p.dtype != torch.float64 or not p.is_contiguous() or _dev_index(p) != dev:
+            raise ValueError("each P must be a contiguous float64 vector of length 2^n on one device")
+        arr[i].n_meas, arr[i].n_mat, arr[i].prob = n, 0, p.data_ptr()
+    L = load_library()
+    ctx = context(dev)
+    need = ctypes.c_size_t()
+    _check(L.qpe_estimate_workspace_size(len(probs), ctypes.byref(need)), "qpe_estimate_workspace_size")
+    ws = _alloc_ws(need.value, dev)
+    out = torch.empty(ESTIMATES_BYTES * len(probs), dtype=torch.uint8, device=f"cuda:{dev}")
+    _check(L.qpe_estimate(ctx.handle, arr, len(probs), out.data_ptr(), ws.data_ptr(), ws.numel()),
+           "qpe_estimate", ctx.handle)
+    torch.cuda.current_stream(dev).synchronize()
+    return np.frombuffer(out.cpu().numpy().tobytes(), dtype=ESTIMATES_DTYPE).copy()
 
 
 def powers(U: torch.Tensor, count_k: int, flags: int = 0, report: bool = False):

@@ -114,6 +114,17 @@ def test_null_context(L):
     assert L.qpe_last_error(None) == b""
 
 
+def test_estimate_host_checks(L):
+    out = ctypes.c_size_t()
+    assert L.qpe_estimate_workspace_size(0, ctypes.byref(out)) == 1
+    assert L.qpe_estimate_workspace_size(3, ctypes.byref(out)) == 0
+    one = ctypes.c_size_t()
+    assert L.qpe_estimate_workspace_size(1, ctypes.byref(one)) == 0
+    assert out.value == 3 * one.value and one.value % 256 == 0 and one.value > 0
+    p = _problems([(8, 0)])
+    assert L.qpe_estimate(None, p, 1, 0x1000, 0x100000, 1 << 20) == 1
+
+
 def test_stage_workspace_sizes(L):
     out = ctypes.c_size_t()
     assert L.qpe_powers_workspace_size(10, ctypes.byref(out)) == 0

@@ -1,0 +1,86 @@
+"""Phase estimators on the device (paper section 4.2) against the oracle's
+estimators on the same probability vectors, and the precision study."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.qpe_oracle as O
+from tests.libutil import ensure_built
+from workloads import eigenbasis_problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qpe():
+    ensure_built()
+    from paper_2507_17175_amd import qpe as q
+    return q
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n,phi", [(1, 0.3), (5, 5 / 32), (10, 0.3), (13, 0.999), (20, 0.123456),
+                                   (22, 0.5 + 2.0 ** -23)])
+def test_estimates_match_oracle_on_same_P(qpe, n, phi):
+    P = O.fejer(phi, n)
+    e = qpe.estimate([_dev(P)])[0]
+    assert e["argmax_index"] == int(np.argmax(P))
+    assert e["argmax_phase"] == O.estimate_argmax(P)
+    assert abs(e["weighted_phase"] - O.estimate_weighted(P)) < 1e-13
+    assert O.phase_error(e["circular_phase"], O.estimate_circular(P)) < 1e-12
+    assert abs(e["prob_sum"] - P.sum()) < 1e-13
+
+
+def test_estimates_batch_uneven(qpe):
+    rng = np.random.default_rng(7)
+    Ps = [O.fejer(float(rng.random()), n) for n in (3, 17, 9, 12)]
+    es = qpe.estimate([_dev(P) for P in Ps])
+    for P, e in zip(Ps, es):
+        assert e["argmax_index"] == int(np.argmax(P))
+        assert abs(e["weighted_phase"] - O.estimate_weighted(P)) < 1e-13
+        assert O.phase_error(e["circular_phase"], O.estimate_circular(P)) < 1e-12
+
+
+def test_argmax_ties_across_blocks_and_nan(qpe):
+    n = 20
+    P = np.random.default_rng(3).random(1 << n) * 0.5
+    for m in (700000, 300000, 5):
+        P[m] = 0.9
+    P[2] = np.nan
+    e = qpe.estimate([_dev(P)])[0]
+    assert e["argmax_index"] == 5  # smallest of the tied maxima; NaN never chosen
+    assert np.isnan(e["prob_sum"])
+
+
+def test_run_then_estimate_vs_oracle(qpe):
+    # end to end on a small eigenbasis set: the estimators of the device P
+    # against the oracle's estimators of the oracle P
+    probs = eigenbasis_problems(9, n_mat=3, seed=21)
+    U = _dev(probs[0].U)
+    Pd = qpe.run_batch([(U, _dev(p.psi), p.n_meas) for p in probs], form="mixed")
+    es = qpe.estimate(Pd)
+    for p, Pg, e in zip(probs, Pd, es):
+        Po = O.qpe_probs(p.U, p.psi, p.n_meas)
+        Pg = Pg.cpu().numpy()
+        dsum = np.abs(Pg - Po).sum()
+        if abs(np.sort(Po)[-1] - np.sort(Po)[-2]) > 1e-6:
+            assert e["argmax_phase"] == O.estimate_argmax(Po)
+        assert abs(e["weighted_phase"] - O.estimate_weighted(Po)) <= 2 * dsum + 1e-13
+        assert O.phase_error(e["argmax_phase"], p.phis[p.coeff_idx[0]]) <= (0.5 + 1e-3) / p.N
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_precision_study_halves_per_qubit(qpe, form):
+    from paper_2507_17175_amd import study
+    probs = eigenbasis_problems(6, n_mat=4, seed=12)
+    U = _dev(probs[0].U)
+    psis = [_dev(p.psi) for p in probs]
+    rows = study.precision_study(U, psis, probs[0].phis, range(6, 21), form=form)
+    for r in rows:
+        assert r["argmax_max"] <= (0.5 + 1e-3) / (1 << r["n_meas"])
+        assert abs(r["prob_sum_min"] - 1) < 1e-5 and abs(r["prob_sum_max"] - 1) < 1e-5
+    slope = study.halving_slope(rows)
+    assert -1.3 < slope < -0.7, slope

@@ -44,3 +44,37 @@ def test_error_halves_per_qubit_trend():
         errs.append(np.mean([O.phase_error(O.estimate_argmax(O.fejer(p, n)), p) for p in phis]))
     ratios = np.array(errs[1:]) / np.array(errs[:-1])
     assert np.all(ratios > 0.3) and np.all(ratios < 0.7), ratios
+
+
+def _circular_closed_form(phi, n):
+    # For eigenvector input, sum_m P(m) exp(2 pi i m / N) with
+    # P(m) = |N^-1 sum_j exp(2 pi i j (phi - m/N))|^2 expands to
+    # N^-2 sum_{j,j'} exp(2 pi i (j - j') phi) sum_m exp(2 pi i m (1 - j + j') / N);
+    # the inner sum is N when j - j' = 1 (N - 1 pairs) or j - j' = 1 - N
+    # (one pair), and 0 otherwise.
+    N = 1 << n
+    z = ((N - 1) * np.exp(2j * np.pi * phi) + np.exp(2j * np.pi * (1 - N) * phi)) / N
+    a = np.angle(z) / (2 * np.pi)
+    return a + 1.0 if a < 0 else a
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 12])
+def test_circular_estimator_closed_form(n):
+    rng = np.random.default_rng(100 + n)
+    for phi in list(rng.random(6)) + [0.0, 0.999, 3 / 8]:
+        est = O.estimate_circular(O.fejer(phi, n))
+        ref = _circular_closed_form(phi, n)
+        assert O.phase_error(est, ref) < 1e-11, (phi, est, ref)
+
+
+def test_circular_estimator_exact_bit_and_wrap():
+    # exact-bit phase: the estimate is the phase itself
+    P = O.fejer(5 / 32, 5)
+    assert abs(O.estimate_circular(P) - 5 / 32) < 1e-15
+    # weight split over m = 0 and m = N - 1: the circular mean sits at the
+    # wrap (1 - 1/(2N)), the plain weighted average in the middle
+    N = 16
+    P = np.zeros(N)
+    P[0] = P[N - 1] = 0.5
+    assert abs(O.estimate_circular(P) - (1 - 0.5 / N)) < 1e-14
+    assert abs(O.estimate_weighted(P) - (N - 1) / (2 * N)) < 1e-15

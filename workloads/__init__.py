@@ -32,6 +32,7 @@ __all__ = [
     "config_problems",
     "CONFIG_NAMES",
     "analytic_problem",
+    "eigenbasis_problems",
 ]
 
 
@@ -162,6 +163,21 @@ def analytic_problem(n_meas: int, n_mat: int, j: int) -> Problem:
     return Problem(n_meas, n_mat, np.ascontiguousarray(U), psi, phis=phis,
                    coeff_idx=np.array([j]), coeffs=np.array([1.0 + 0j]), Q=P,
                    label=f"analytic-n{n_meas}-t{n_mat}-j{j}")
+
+
+def eigenbasis_problems(n_meas: int, n_mat: int = 4, seed: int = 12) -> List[Problem]:
+    """One Haar unitary with uniform eigenphases and each of its d eigenvectors
+    as the input of its own instance (the paper's precision evaluation,
+    section 4.2, runs every eigenvector of a 16 x 16 random unitary). Every
+    instance shares U; instance i has psi = Q[:, i] and phase phis[i]."""
+    d = 1 << n_mat
+    rng = np.random.default_rng(seed)
+    q = haar_unitary(d, rng)
+    phis = rng.random(d)
+    U = unitary_from_phases(q, phis)
+    return [Problem(n_meas, n_mat, U, np.ascontiguousarray(q[:, i].copy()), phis=phis,
+                    coeff_idx=np.array([i]), coeffs=np.array([1.0 + 0j]), Q=q,
+                    label=f"eigenbasis-n{n_meas}-t{n_mat}-i{i}") for i in range(d)]
 
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4")
