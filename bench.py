@@ -178,6 +178,43 @@ def precision_study_main(a) -> int:
     return 0
 
 
+def end_to_end(qpe, torch, p, form="mixed", reps=3):
+    """One circuit from host inputs to host probabilities, split the way the
+    paper's profile splits it (allocation, host-to-device copies, the
+    application of the circuit, device-to-host copy). The device workspace
+    is allocated fresh each time (the caching allocator emptied first); U and
+    psi come from pinned host memory. Median over reps."""
+    U_h = torch.from_numpy(p.U).pin_memory()
+    psi_h = torch.from_numpy(p.psi).pin_memory()
+    shapes = [(p.n_meas, p.n_mat)]
+    need = qpe.workspace_bytes(shapes, form)
+    rows = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U_d = U_h.to("cuda", non_blocking=True)
+        psi_d = psi_h.to("cuda", non_blocking=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        P_d = qpe.run_batch([(U_d, psi_d, p.n_meas)], form=form, workspace=ws)[0]
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        P_h = P_d.cpu()
+        t4 = time.perf_counter()
+        rows.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3, t4 - t0))
+        del ws, U_d, psi_d, P_d, P_h
+    med = np.median(np.array(rows), axis=0) * 1e3
+    return {"alloc_ms": round(float(med[0]), 3), "h2d_ms": round(float(med[1]), 3), "run_ms": round(float(med[2]), 3),
+            "d2h_ms": round(float(med[3]), 3), "total_ms": round(float(med[4]), 3),
+            "circuits_per_s_incl_transfers": round(1e3 / float(med[4]), 3),
+            "h2d_bytes": int(p.U.nbytes + p.psi.nbytes), "d2h_bytes": int(8 << p.n_meas),
+            "workspace_bytes": int(need), "reps": reps}
+
+
 def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
     run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])], form=form, flags=flags)
     for _ in range(warmup):
@@ -272,6 +309,8 @@ def main():
         "bitwise_equal_to_gate_route": bool(np.array_equal(P_dbl, P_mixed)),
         "breakdown": {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing_d.items()},
     }
+
+    out["end_to_end_mixed"] = end_to_end(qpe, torch, p, "mixed")
 
     if not a.no_fp64:
         fsteps = a.fp64_steps or max(3, a.steps // 2)

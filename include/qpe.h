@@ -143,6 +143,19 @@ qpe_status qpe_run(qpe_ctx *ctx, const qpe_problem *problems, int count, int for
                    unsigned flags, void *workspace, size_t workspace_bytes,
                    qpe_report *report);
 
+/* One instance as qpe_run (count 1), also returning the final statevector:
+ * the paper's emulator outputs the statevector after the inverse QFT
+ * (section 3), whose norms give the outcome distribution. state_out
+ * (device, caller-owned, N*d elements) receives A[m, r] of the formula at the
+ * top of this header, row-major in natural outcome order m: complex64 for
+ * QPE_FORM_MIXED, complex128 for QPE_FORM_FP64. prob and report are written
+ * as by qpe_run. Same workspace as qpe_run for this one problem.
+ * Errors: as qpe_run; QPE_ERR_ALIGN if state_out is not aligned to its
+ * element size. */
+qpe_status qpe_run_state(qpe_ctx *ctx, const qpe_problem *problem, int form, unsigned flags,
+                         void *workspace, size_t workspace_bytes, void *state_out,
+                         qpe_report *report);
+
 /* Host-only pre-flight: the status qpe_run would return for these arguments
  * before it touches the context or the device (QPE_OK if they are valid).
  * Never dereferences device pointers. */

@@ -297,6 +297,35 @@ __global__ void __launch_bounds__(kThreads) k_prob(const T* __restrict__ X, doub
     prob_rows<T>(X, prob, n, t, plan, scale, base);
 }
 
+// Row position of outcome m after the DFT passes (the inverse of prob_index):
+// bits [B_q, B_{q+1}) of m move to bits [n - B_{q+1}, n - B_q) of p.
+__device__ inline int64_t state_position(int64_t m, int n, const DftPlan& plan) {
+  int64_t p = 0;
+  int hi = n, lo = 0;
+  for (int q = 0; q < plan.npass; ++q) {
+    hi -= plan.bits[q];
+    const int64_t digit = (m >> lo) & ((int64_t(1) << plan.bits[q]) - 1);
+    p |= digit << hi;
+    lo += plan.bits[q];
+  }
+  return p;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gather_state(const T* __restrict__ X, T* __restrict__ out, int n, int t,
+                                                           DftPlan plan, double scale) {
+  const int64_t total = int64_t(1) << (n + t);
+  const int64_t dmask = (int64_t(1) << t) - 1;
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
+    const int64_t m = e >> t, r = e & dmask;
+    const T v = X[(state_position(m, n, plan) << t) + r];
+    T o;
+    o.x = decltype(v.x)(double(v.x) * scale);
+    o.y = decltype(v.y)(double(v.y) * scale);
+    out[e] = o;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
                                                      const double2* __restrict__ psi, int t,
                                                      const unsigned long long* __restrict__ defect_bits,
@@ -481,6 +510,18 @@ hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, i
     hipLaunchKernelGGL(k_h_broadcast_c128, dim3(grid_for(total)), dim3(kThreads), 0, s,
                        static_cast<const double2*>(psi), static_cast<double2*>(state), total, (1 << t) - 1, scale);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_state(bool mixed, const void* X, void* out, int n, int t, const DftPlan& plan, double scale,
+                               hipStream_t s) {
+  const int64_t total = int64_t(1) << (n + t);
+  if (mixed)
+    hipLaunchKernelGGL(k_gather_state<float2>, dim3(grid_for(total)), dim3(kThreads), 0, s,
+                       static_cast<const float2*>(X), static_cast<float2*>(out), n, t, plan, scale);
+  else
+    hipLaunchKernelGGL(k_gather_state<double2>, dim3(grid_for(total)), dim3(kThreads), 0, s,
+                       static_cast<const double2*>(X), static_cast<double2*>(out), n, t, plan, scale);
   return hipGetLastError();
 }
 

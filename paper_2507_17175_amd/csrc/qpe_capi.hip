@@ -11,6 +11,7 @@
 //   readout        P(m) = sum_r |A[m, r]|^2 in FP64, digit order undone
 // Nothing here allocates device memory: all scratch lives in the caller's
 // workspace, so a run can be captured into a HIP graph.
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -605,6 +606,26 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
   if (count == 1) return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report);
   return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report);
+}
+
+QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags,
+                                 void* workspace, size_t workspace_bytes, void* state_out, qpe_report* report) {
+  if (!ctx || !state_out) return QPE_ERR_ARG;
+  qpe_status s = qpe_check_run(problem, 1, form, flags, workspace, workspace_bytes, report);
+  if (s != QPE_OK) return s;
+  if (misaligned(state_out, form == QPE_FORM_MIXED ? 8 : 16)) return QPE_ERR_ALIGN;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  s = run_one(ctx, *problem, form, flags, static_cast<char*>(workspace), report);
+  if (s != QPE_OK) return s;
+  const int n = problem->n_meas, t = problem->n_mat;
+  const RunLayout L = run_layout(n, t, form, flags);
+  // the DFT passes leave the transform unnormalised: A = 2^(-n/2) X
+  const double scale = std::ldexp(1.0, -(n / 2)) * ((n & 1) ? std::sqrt(0.5) : 1.0);
+  QPE_HIP(ctx, launch_gather_state(form == QPE_FORM_MIXED, static_cast<char*>(workspace) + L.state0, state_out, n,
+                                   t, make_dft_plan(n), scale, ctx->stream));
+  return QPE_OK;
 }
 
 // ------------------------------------------------------------ stage entries

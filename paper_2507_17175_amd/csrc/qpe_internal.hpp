@@ -299,6 +299,10 @@ hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t
                        hipStream_t s);
 hipError_t launch_report(const double* prob, int n, const double2* psi, int t,
                          const unsigned long long* defect_bits, void* report, hipStream_t s);
+// Final statevector in outcome order: out[m][r] = scale * X[p][r] where row
+// position p of the DFT output holds outcome m (prob_index(p) = m).
+hipError_t launch_gather_state(bool mixed, const void* X, void* out, int n, int t, const DftPlan& plan, double scale,
+                               hipStream_t s);
 hipError_t launch_copy_rows_back(bool mixed, void* state, const void* other, int n, int t, int k,
                                  hipStream_t s);
 

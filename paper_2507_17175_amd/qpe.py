@@ -40,6 +40,7 @@ EXPORTS = (
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
     "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
+    "qpe_run_state",
 )
 
 KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2}
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_kernel_variants": (st, [i32, ctypes.POINTER(i32)]),
             "qpe_ctx_set_variant": (st, [vp, i32, i32, i32]),
             "qpe_ctx_read_timing": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+            "qpe_run_state": (st, [vp, ctypes.POINTER(Problem), i32, ctypes.c_uint, vp, sz, vp, vp]),
             "qpe_estimate_workspace_size": (st, [i32, ctypes.POINTER(sz)]),
             "qpe_estimate": (st, [vp, ctypes.POINTER(Problem), i32, vp, vp, sz]),
             "qpe_status_string": (ctypes.c_char_p, [i32]),
@@ -266,6 +268,33 @@ def run(U: torch.Tensor, psi: torch.Tensor, n_meas: int, form="mixed", flags: in
     if report:
         return out[0][0], out[1][0]
     return out[0]
+
+
+def run_state(U: torch.Tensor, psi: torch.Tensor, n_meas: int, form="mixed", flags: int = 0):
+    """QPE probabilities and the final statevector A (2^n_meas x d, natural
+    outcome order; complex64 for the mixed form, complex128 for FP64)."""
+    d = U.shape[0]
+    t = d.bit_length() - 1
+    if d != (1 << t):
+        raise ValueError("U must be 2^t x 2^t")
+    _need(U, torch.complex128, (d, d), "U")
+    _need(psi, torch.complex128, (d,), "psi")
+    dev = _dev_index(U)
+    f = _form(form)
+    arr = (Problem * 1)()
+    prob = torch.empty(1 << int(n_meas), dtype=torch.float64, device=U.device)
+    state = torch.empty((1 << int(n_meas), d), dtype=torch.complex64 if f == FORM_MIXED else torch.complex128,
+                        device=U.device)
+    arr[0].n_meas, arr[0].n_mat = int(n_meas), t
+    arr[0].U, arr[0].psi, arr[0].prob = U.data_ptr(), psi.data_ptr(), prob.data_ptr()
+    L = load_library()
+    ctx = context(dev)
+    need = ctypes.c_size_t()
+    _check(L.qpe_workspace_size(arr, 1, f, flags, ctypes.byref(need)), "qpe_workspace_size")
+    ws = _alloc_ws(need.value, dev)
+    _check(L.qpe_run_state(ctx.handle, arr, f, flags, ws.data_ptr(), ws.numel(), state.data_ptr(), None),
+           "qpe_run_state", ctx.handle)
+    return prob, state
 
 
 def estimate(probs: Sequence[torch.Tensor]) -> np.ndarray:

@@ -84,3 +84,17 @@ def test_precision_study_halves_per_qubit(qpe, form):
         assert abs(r["prob_sum_min"] - 1) < 1e-5 and abs(r["prob_sum_max"] - 1) < 1e-5
     slope = study.halving_slope(rows)
     assert -1.3 < slope < -0.7, slope
+
+
+def test_batch_beyond_one_grid_matches_fejer(qpe):
+    # 16 instances of 2^24 x 16 amplitudes: the grouped readout launch has
+    # 2^24 workgroups and is split into several grids; every instance must
+    # still equal the closed form (eigenvector input).
+    probs = eigenbasis_problems(24, n_mat=4, seed=12)
+    U = _dev(probs[0].U)
+    Pd = qpe.run_batch([(U, _dev(p.psi), p.n_meas) for p in probs], form="mixed")
+    for p, Pg in zip(probs, Pd):
+        F = O.fejer(p.phis[p.coeff_idx[0]], p.n_meas)
+        err = float(np.abs(Pg.cpu().numpy() - F).max())
+        assert err <= 1e-6, (p.label, err)
+        del F
