@@ -127,9 +127,12 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--study", choices=["precision"], default=None,
+    ap.add_argument("--study", choices=["precision", "scaling"], default=None,
                     help="precision: the estimator study (section 4.2) over every eigenvector of a 16 x 16 Haar "
-                         "unitary for n = --study-n-min .. --study-n-max; prints one JSON line and exits")
+                         "unitary for n = --study-n-min .. --study-n-max; scaling: time and device memory "
+                         "against N_total (section 4.1) on the analytic test problem, N_total = 6 .. "
+                         "--study-total-max; each prints one JSON line and exits")
+    ap.add_argument("--study-total-max", type=int, default=28)
     ap.add_argument("--study-n-min", type=int, default=4)
     ap.add_argument("--study-n-max", type=int, default=24)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -215,6 +218,37 @@ def end_to_end(qpe, torch, p, form="mixed", reps=3):
             "workspace_bytes": int(need), "reps": reps}
 
 
+def scaling_study_main(a) -> int:
+    """Section 4.1 sweeps on the analytic test problem (known eigenphases
+    j / 2^N_mat; U = P Lambda P^-1 is not unitary, so the powers skip the
+    Newton-Schulz step): N_mat = min(N_total // 2, 12), N_meas = the rest,
+    input the eigenvector of j = d / 3, whose phase is exact in N_meas >=
+    N_mat bits, so all probability must sit at m = j 2^(N_meas - N_mat)."""
+    import torch
+    from paper_2507_17175_amd import qpe, study
+    from workloads import analytic_problem
+
+    qpe.load_library()
+    cases = []
+    for total in range(6, a.study_total_max + 1):
+        t = min(total // 2, 12)
+        n = total - t
+        j = (1 << t) // 3
+        p = analytic_problem(n, t, j)
+        cases.append({"U": torch.from_numpy(p.U).cuda(), "psi": torch.from_numpy(p.psi).cuda(), "n": n,
+                      "peak": j << (n - t)})
+    t0 = time.perf_counter()
+    rows = []
+    for c in cases:
+        rows += study.scaling_sweep([c], flags=qpe.NO_POLAR)
+        print(json.dumps({"progress": rows[-1]}), file=sys.stderr, flush=True)
+        del c["U"], c["psi"]
+    out = {"study": "time and device memory vs N_total (section 4.1), analytic test problem (section 3)",
+           "rows": rows, "seconds": round(time.perf_counter() - t0, 2)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
     run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])], form=form, flags=flags)
     for _ in range(warmup):
@@ -244,6 +278,8 @@ def main():
         return copy_probe(a.copy_probe_mib)
     if a.study == "precision":
         return precision_study_main(a)
+    if a.study == "scaling":
+        return scaling_study_main(a)
     import torch
     from paper_2507_17175_amd import qpe
     from workloads import config_problems

@@ -58,3 +58,51 @@ def halving_slope(rows: List[Dict], key: str = "argmax_mean") -> float:
     e = np.log2(np.array([r[key] for r in rows], dtype=np.float64))
     A = np.vstack([n, np.ones_like(n)]).T
     return float(np.linalg.lstsq(A, e, rcond=None)[0][0])
+
+
+def scaling_sweep(cases: Sequence[Dict], forms=("mixed", "fp64"), flags: int = 0, reps: int = 3) -> List[Dict]:
+    """Time per circuit and memory against the total qubit count (the paper's
+    section 4.1 sweeps, which use matrices with known eigenphases).
+
+    cases: dicts with keys U, psi (device complex128), n (measurement
+    qubits) and, optionally, peak (the outcome index that must carry all the
+    probability). One row per (case, form): median time of `reps` circuits
+    after one warm-up, the exact workspace the library asked for, the peak
+    device memory the process held during the run, and the double-precision
+    statevector size 16 * 2^(n + t) the paper plots as the lower bound."""
+    rows = []
+    for c in cases:
+        U, psi, n = c["U"], c["psi"], int(c["n"])
+        t = U.shape[0].bit_length() - 1
+        for form in forms:
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            need = qpe.workspace_bytes([(n, t)], form, flags)
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=U.device)
+            P = qpe.run_batch([(U, psi, n)], form=form, flags=flags, workspace=ws)[0]
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                P = qpe.run_batch([(U, psi, n)], form=form, flags=flags, workspace=ws)[0]
+                ev1.record()
+                torch.cuda.synchronize()
+                times.append(ev0.elapsed_time(ev1))
+            peak = torch.cuda.max_memory_allocated() - base
+            row = {"n_total": n + t, "n_meas": n, "n_mat": t, "form": form,
+                   "ms_per_circuit": round(float(np.median(times)), 4),
+                   "workspace_bytes": int(need), "peak_device_bytes": int(peak),
+                   "fp64_statevector_bytes": int(16 << (n + t)),
+                   "peak_over_fp64_statevector": round(peak / float(16 << (n + t)), 4)}
+            if c.get("peak") is not None:
+                Ph = P.cpu().numpy()
+                k = int(c["peak"])
+                row["prob_at_peak"] = float(Ph[k])
+                Ph[k] -= 1.0
+                row["max_abs_err_vs_exact"] = float(np.abs(Ph).max())
+            rows.append(row)
+            del ws, P
+    return rows
