@@ -127,6 +127,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in tile variants instead of running the autotuner first")
     ap.add_argument("--study", choices=["precision", "scaling"], default=None,
                     help="precision: the estimator study (section 4.2) over every eigenvector of a 16 x 16 Haar "
                          "unitary for n = --study-n-min .. --study-n-max; scaling: time and device memory "
@@ -293,6 +295,15 @@ def main():
     N, d = 1 << n, 1 << t
     prob = {"U": torch.from_numpy(p.U).cuda(), "psi": torch.from_numpy(p.psi).cuda(), "n": n}
 
+    tuned = {}
+    if not a.no_autotune:
+        # the autotuner picks the tile variants of this operator size (a few
+        # circuits per variant, before and outside the timed region)
+        ctx = qpe.context(torch.cuda.current_device())
+        tuned["mixed"] = ctx.autotune(prob["U"], prob["psi"], n, form="mixed", reps=2)
+        if not a.no_fp64:
+            tuned["fp64"] = ctx.autotune(prob["U"], prob["psi"], n, form="fp64", reps=1)
+
     el, timing, rep, P_mixed = time_form(qpe, torch, prob, "mixed", a.steps, a.warmup)
     ms_per = 1e3 * el / a.steps
     value = a.steps / el
@@ -327,6 +338,7 @@ def main():
         "config": {"workload": CONFIGS[a.config], "n_meas": n, "n_mat": t, "amplitudes": N * d,
                    "state": "complex64", "U": "complex128", "form": "mixed"},
         "roofline": roofline,
+        "autotune": tuned or None,
         "breakdown_mixed": breakdown,
         "report_mixed": {"prob_sum": float(rep["prob_sum"]), "unitarity_defect": float(rep["unitarity_defect"]),
                          "flags": int(rep["flags"])},

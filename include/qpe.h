@@ -256,7 +256,7 @@ qpe_status qpe_ctx_enable_timing(qpe_ctx *ctx, int max_pairs);
 qpe_status qpe_ctx_reset_timing(qpe_ctx *ctx);
 qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *total_ms);
 
-/* ---- kernel variants (tile shapes), chosen by an offline autotuner ----
+/* ---- kernel variants (tile shapes), chosen by the autotuner below ----
  * Each kernel class has variants 1..count (different tile shapes and
  * pipelining); 0 selects the built-in default. A context applies its
  * choice to every later call. All variants compute the same result up to
@@ -271,6 +271,27 @@ qpe_status qpe_kernel_variants(int kernel_class, int *count);
 /* n_mat selects the operator size the choice applies to (0..QPE_MAX_N_MAT),
  * or -1 for every size. */
 qpe_status qpe_ctx_set_variant(qpe_ctx *ctx, int kernel_class, int n_mat, int variant);
+
+/* The variant the context currently uses for a class and operator size. */
+qpe_status qpe_ctx_get_variant(const qpe_ctx *ctx, int kernel_class, int n_mat, int *variant);
+
+/* Autotuner (the tile shapes of the batched-GEMM pattern are picked by
+ * measurement, not fixed): for each kernel class this problem uses (the
+ * power-chain GEMM; the controlled GEMM of its form when d >= 32), run the
+ * whole circuit with every variant of that class, 0 (the built-in default)
+ * included, and keep the fastest for the problem's n_mat in the context. The
+ * timed runs are one warm-up plus `reps` (1..1000) circuits per variant,
+ * bracketed by HIP events on the context stream; the call SYNCHRONISES that
+ * stream and is not capturable. The problem's prob vector is overwritten.
+ * chosen: host int[QPE_KERNEL_COUNT], the variant in place for every class
+ * afterwards (unchanged for classes not tuned). class_ms: host
+ * double[QPE_KERNEL_COUNT * QPE_TUNE_MAX_VARIANTS] or NULL: mean ms per
+ * circuit of each (class, variant) tried, -1 where not tried.
+ * Errors: as qpe_run; QPE_ERR_ARG for reps out of range or chosen NULL. */
+#define QPE_TUNE_MAX_VARIANTS 8
+qpe_status qpe_autotune(qpe_ctx *ctx, const qpe_problem *problem, int form, unsigned flags,
+                        void *workspace, size_t workspace_bytes, int reps, int *chosen,
+                        double *class_ms);
 
 /* ---- misc ---- */
 

@@ -499,6 +499,78 @@ QPE_API qpe_status qpe_ctx_set_variant(qpe_ctx* ctx, int kernel_class, int n_mat
   return QPE_OK;
 }
 
+QPE_API qpe_status qpe_ctx_get_variant(const qpe_ctx* ctx, int kernel_class, int n_mat, int* variant) {
+  if (!ctx || !variant || variant_count(kernel_class) < 0) return QPE_ERR_ARG;
+  if (n_mat < 0 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
+  *variant = ctx->variant[kernel_class][n_mat];
+  return QPE_OK;
+}
+
+// Autotuner: for each kernel class the problem uses, time whole circuits
+// with every variant of that class (the other stages do not change) and keep
+// the fastest for this n_mat. Classes are tuned one after another, each with
+// the choices made so far in place.
+QPE_API qpe_status qpe_autotune(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags, void* workspace,
+                                size_t workspace_bytes, int reps, int* chosen, double* class_ms) {
+  if (!ctx || !chosen) return QPE_ERR_ARG;
+  if (reps < 1 || reps > 1000) return QPE_ERR_ARG;
+  qpe_status s = qpe_check_run(problem, 1, form, flags, workspace, workspace_bytes, nullptr);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  const int t = problem->n_mat;
+  const bool mixed = form == QPE_FORM_MIXED;
+  bool uses[QPE_KERNEL_COUNT] = {};
+  uses[QPE_KERNEL_ZGEMM] = problem->n_meas >= 2;
+  uses[QPE_KERNEL_CTRL_MIXED] = mixed && t >= 5;
+  uses[QPE_KERNEL_CTRL_F64] = !mixed && t >= 5;
+  if (class_ms)
+    for (int i = 0; i < QPE_KERNEL_COUNT * QPE_TUNE_MAX_VARIANTS; ++i) class_ms[i] = -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  // timing a run with the per-launch timers on would time them too
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  qpe_status st = QPE_OK;
+  char* ws = static_cast<char*>(workspace);
+  for (int c = 0; c < QPE_KERNEL_COUNT && st == QPE_OK; ++c) {
+    chosen[c] = ctx->variant[c][t];
+    if (!uses[c]) continue;
+    const int nv = variant_count(c);
+    double best = 1e300;
+    int best_v = 0;
+    for (int v = 0; v <= nv && v < QPE_TUNE_MAX_VARIANTS && st == QPE_OK; ++v) {
+      ctx->variant[c][t] = v;
+      st = run_one(ctx, *problem, form, flags, ws, nullptr);  // warm-up
+      if (st != QPE_OK) break;
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = hip_fail(ctx, hipErrorUnknown, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && st == QPE_OK; ++r) st = run_one(ctx, *problem, form, flags, ws, nullptr);
+      if (st != QPE_OK) break;
+      hipError_t he = hipEventRecord(e1, ctx->stream);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) { st = hip_fail(ctx, he, "autotune timing"); break; }
+      const double per = double(ms) / reps;
+      if (class_ms) class_ms[c * QPE_TUNE_MAX_VARIANTS + v] = per;
+      if (per < best) {
+        best = per;
+        best_v = v;
+      }
+    }
+    ctx->variant[c][t] = best_v;
+    chosen[c] = best_v;
+  }
+  ctx->timing = was_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 QPE_API qpe_status qpe_ctx_set_stream(qpe_ctx* ctx, void* stream) {
   if (!ctx) return QPE_ERR_ARG;
   ctx->stream = static_cast<hipStream_t>(stream);

@@ -40,10 +40,11 @@ EXPORTS = (
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
     "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
-    "qpe_run_state",
+    "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune",
 )
 
 KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2}
+TUNE_MAX_VARIANTS = 8
 
 TIMERS = {"ctrl_gemm": 0, "powers": 1, "split": 2, "qft": 3, "prob": 4, "hlayer": 5}
 
@@ -108,6 +109,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_ctx_set_variant": (st, [vp, i32, i32, i32]),
             "qpe_ctx_read_timing": (st, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
             "qpe_run_state": (st, [vp, ctypes.POINTER(Problem), i32, ctypes.c_uint, vp, sz, vp, vp]),
+            "qpe_ctx_get_variant": (st, [vp, i32, i32, ctypes.POINTER(i32)]),
+            "qpe_autotune": (st, [vp, ctypes.POINTER(Problem), i32, ctypes.c_uint, vp, sz, i32,
+                                  ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
             "qpe_estimate_workspace_size": (st, [i32, ctypes.POINTER(sz)]),
             "qpe_estimate": (st, [vp, ctypes.POINTER(Problem), i32, vp, vp, sz]),
             "qpe_status_string": (ctypes.c_char_p, [i32]),
@@ -151,6 +155,58 @@ class Context:
         operators of 2^n_mat (-1: all sizes)."""
         _check(load_library().qpe_ctx_set_variant(self.handle, KERNEL_CLASSES[kernel_class], int(n_mat),
                                                   int(variant)), "qpe_ctx_set_variant", self.handle)
+
+    def get_variant(self, kernel_class: str, n_mat: int) -> int:
+        v = ctypes.c_int()
+        _check(load_library().qpe_ctx_get_variant(self.handle, KERNEL_CLASSES[kernel_class], int(n_mat),
+                                                  ctypes.byref(v)), "qpe_ctx_get_variant", self.handle)
+        return v.value
+
+    def tuning_table(self) -> Dict[str, Dict[int, int]]:
+        """Every non-default choice, {class: {n_mat: variant}} (JSON-friendly)."""
+        out: Dict[str, Dict[int, int]] = {}
+        for name in KERNEL_CLASSES:
+            for t in range(0, 16):
+                v = self.get_variant(name, t)
+                if v:
+                    out.setdefault(name, {})[t] = v
+        return out
+
+    def apply_tuning_table(self, table: Dict[str, Dict[int, int]]) -> None:
+        for name, per in table.items():
+            for t, v in per.items():
+                self.set_variant(name, int(v), int(t))
+
+    def autotune(self, U: torch.Tensor, psi: torch.Tensor, n_meas: int, form="mixed", flags: int = 0,
+                 reps: int = 3) -> Dict:
+        """Time every tile variant of the kernel classes this problem uses and
+        keep the fastest in this context (see qpe_autotune). Synchronises."""
+        d = U.shape[0]
+        t = d.bit_length() - 1
+        _need(U, torch.complex128, (d, d), "U")
+        _need(psi, torch.complex128, (d,), "psi")
+        f = _form(form)
+        arr = (Problem * 1)()
+        prob = torch.empty(1 << int(n_meas), dtype=torch.float64, device=U.device)
+        arr[0].n_meas, arr[0].n_mat = int(n_meas), t
+        arr[0].U, arr[0].psi, arr[0].prob = U.data_ptr(), psi.data_ptr(), prob.data_ptr()
+        L = load_library()
+        self.bind_current_stream()
+        need = ctypes.c_size_t()
+        _check(L.qpe_workspace_size(arr, 1, f, flags, ctypes.byref(need)), "qpe_workspace_size")
+        ws = _alloc_ws(need.value, self.device)
+        chosen = (ctypes.c_int * len(KERNEL_CLASSES))()
+        ms = (ctypes.c_double * (len(KERNEL_CLASSES) * TUNE_MAX_VARIANTS))()
+        _check(L.qpe_autotune(self.handle, arr, f, flags, ws.data_ptr(), ws.numel(), int(reps), chosen, ms),
+               "qpe_autotune", self.handle)
+        out = {"n_mat": t, "chosen": {}, "ms_per_circuit": {}}
+        for name, c in KERNEL_CLASSES.items():
+            tried = [round(ms[c * TUNE_MAX_VARIANTS + v], 4) for v in range(TUNE_MAX_VARIANTS)
+                     if ms[c * TUNE_MAX_VARIANTS + v] >= 0]
+            if tried:
+                out["chosen"][name] = chosen[c]
+                out["ms_per_circuit"][name] = tried
+        return out
 
     def enable_timing(self, max_pairs: int = 4096) -> None:
         _check(load_library().qpe_ctx_enable_timing(self.handle, int(max_pairs)), "qpe_ctx_enable_timing",

@@ -125,6 +125,14 @@ def test_estimate_host_checks(L):
     assert L.qpe_estimate(None, p, 1, 0x1000, 0x100000, 1 << 20) == 1
 
 
+def test_autotune_and_variant_host_checks(L):
+    chosen = (ctypes.c_int * 3)()
+    p = _problems([(8, 5)])
+    assert L.qpe_autotune(None, p, 1, 0, 0x100000, 1 << 30, 2, chosen, None) == 1
+    v = ctypes.c_int()
+    assert L.qpe_ctx_get_variant(None, 0, 5, ctypes.byref(v)) == 1
+
+
 def test_stage_workspace_sizes(L):
     out = ctypes.c_size_t()
     assert L.qpe_powers_workspace_size(10, ctypes.byref(out)) == 0
