@@ -27,6 +27,8 @@
 //    consecutive rows then cover all 64 banks once.
 //  * k_ctrl_bf16x6 (variant 1): 4 wave64s, K slab of 32 complex, single
 //    LDS buffer with register prefetch.
+#include <type_traits>
+
 #include "qpe_internal.hpp"
 
 namespace qpe {
@@ -312,6 +314,205 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf
   ctrl_db_tile<BM, BN, WM, WN, IL>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
+// ----------------------------------------------------------------- variant 4
+// Triple-buffered LDS with unpadded 32-byte rows. A row r holds the two
+// 16-byte K chunks of one slab; chunk h sits at position h ^ ((r >> 3) & 1),
+// so the 16 rows that one quarter of a wave touches in a fragment read, an A
+// store (8 bytes per lane) or a B store (16 bytes per lane) cover each bank
+// once. With three buffers the slab s + 1 buffer is complete one barrier
+// earlier than it is needed, so the fragment reads of slab s + 1 are issued
+// before the barrier that ends slab s and their latency overlaps it. The
+// global loads run four slabs ahead; the split of slab s + 2 is stored
+// between the MFMA groups of slab s.
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ctrl_tb_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                             const uint16_t* __restrict__ planes, int n, int t, int k,
+                                             uint64_t pmask, int tile_m, int tile_n) {
+  constexpr int NT = 512;
+  static_assert(WM * WN == 8, "8 waves");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KS = 16;   // complex K per slab
+  constexpr int ROW = 16;  // bf16 per LDS row (32 bytes)
+  constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
+  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int CA = BM * KS / 4 / NT;   // 4-complex A chunks per thread
+  constexpr int NB = 12 * BN;            // 16-byte B chunks per slab
+  constexpr int CB = (NB + NT - 1) / NT;  // per thread (the last one guarded)
+  static_assert(CA >= 1 && CA * NT * 4 == BM * KS, "tile/thread mismatch");
+  static_assert(3 * BUF * 2 <= 160 * 1024, "LDS budget");
+
+  __shared__ __attribute__((aligned(16))) uint16_t lds[3 * BUF];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+  // bf16 offset of 16-byte chunk h of LDS row r
+  auto sw = [](int r, int h) { return r * ROW + 8 * (h ^ ((r >> 3) & 1)); };
+
+  // Rows past M (only when M < BM) read row M-1 (unconditional loads).
+  const float2* src_row[CA];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int c = tid + q * NT;
+    int gi = min(i0 + c / 4, M - 1);
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+  }
+
+  // two register sets: slab s + 2 is split from set s & 1, which was loaded
+  // two slabs earlier, so a global load has two slabs of time to arrive
+  float4 ra[2][CA][2];
+  u32x4 rb[2][CB];
+  auto load_global = [&](auto setc, int s) {
+    constexpr int S = decltype(setc)::value;
+    const int k0 = s * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[S][q][0] = p[0];
+      ra[S][q][1] = p[1];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      rb[S][q] = *reinterpret_cast<const u32x4*>(planes + pl * dd +
+                                                 (int64_t(s) * d + j0 + (w >> 1)) * kPlaneBlock + 8 * (w & 1));
+    }
+  };
+  bf16x4 pc[CA][6];
+  auto split_part = [&](auto setc, int u) {
+    constexpr int S = decltype(setc)::value;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4 w = ra[S][q][u >> 1];
+      __bf16 h, m, l;
+      split3((u & 1) ? w.z : w.x, h, m, l);
+      pc[q][0][u] = h;
+      pc[q][2][u] = m;
+      pc[q][4][u] = l;
+      split3((u & 1) ? w.w : w.y, h, m, l);
+      pc[q][1][u] = h;
+      pc[q][3][u] = m;
+      pc[q][5][u] = l;
+    }
+  };
+  auto write_a = [&](int b) {
+    uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tid + q * NT;
+      int r = c / 4, kq = c & 3;
+      const int off = sw(r, kq >> 1) + 4 * (kq & 1);
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + off) = pc[q][pl];
+    }
+  };
+  auto write_b = [&](auto setc, int b) {
+    constexpr int S = decltype(setc)::value;
+    uint16_t* base = lds + b * BUF + 6 * A_PLANE;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      *reinterpret_cast<u32x4*>(base + pl * B_PLANE + sw(w >> 1, w & 1)) = rb[S][q];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[x][y][v] = 0.f;
+        acc_im[x][y][v] = 0.f;
+      }
+
+  const int lr = lane & 31, kh = lane >> 5;
+  bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+  auto read_frags = [&](int b) {
+    const uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + sw(wi0 + 32 * x + lr, kh));
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bv[y][pl] = *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + sw(wj0 + 32 * y + lr, kh));
+#pragma unroll
+      for (int pc2 = 0; pc2 < 3; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+    }
+  };
+
+  const int nk = d / KS;  // a power of two >= 4 here (d >= 64)
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, 1>;
+  load_global(Set0{}, 0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_part(Set0{}, u);
+  write_a(0);
+  write_b(Set0{}, 0);
+  load_global(Set1{}, 1);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_part(Set1{}, u);
+  write_a(1);
+  write_b(Set1{}, 1);
+  load_global(Set0{}, 2);
+  load_global(Set1{}, 3);
+  __syncthreads();
+  read_frags(0);
+
+  // slab s: MFMAs from buffer s % 3; the split of slab s + 2 (register set
+  // s & 1) goes to buffer (s + 2) % 3 between the MFMA groups; then set s & 1
+  // is reloaded with slab s + 4, and the fragments of slab s + 1 are read.
+  auto slab = [&](auto setc, int s, int bcur) {
+    const int b1 = bcur == 2 ? 0 : bcur + 1;
+    const int b2 = b1 == 2 ? 0 : b1 + 1;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < 4) split_part(setc, c);
+      if (c == 3) write_a(b2);
+      if (c == 4) write_b(setc, b2);
+      if (c == 5) load_global(setc, min(s + 4, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // Slab s + 1 was stored before the previous barrier: read it now. (In
+    // the last iteration this reads a buffer whose contents go unused.)
+    read_frags(b1);
+    __syncthreads();
+    return b1;
+  };
+  int bcur = 0;
+  for (int s = 0; s < nk; s += 2) {
+    bcur = slab(Set0{}, s, bcur);
+    bcur = slab(Set1{}, s + 1, bcur);
+  }
+
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_tb(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_tb_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
 // ----------------------------------------------------------------- variant 1
 template <int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
@@ -516,13 +717,20 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 3; }
+int ctrl_mixed_variants() { return 4; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant) {
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (variant == 4) {
+    // triple-buffered, swizzled LDS
+    if (t >= 7) return launch<512>(k_ctrl_bf16x6_tb<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6) return launch<512>(k_ctrl_bf16x6_tb<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }

@@ -106,3 +106,22 @@ def test_graph_replay_matches_eager(qpe, form):
         out = graph()
         for e, P in zip(eager, out):
             assert np.array_equal(host(P), e), rep
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_graph_replay_single_instance(qpe, flags):
+    # one instance (the single-run path, gate route and prefix doubling),
+    # captured: every replay must equal the eager run
+    p = make_problem(11, 7, np.random.default_rng(77))
+    say("graph capture of one mixed instance", flags)
+    items = [(dev(p.U), dev(p.psi), p.n_meas)]
+    runner = qpe.Runner(items, form="mixed", flags=flags)
+    eager = host(runner()[0]).copy()
+    graph = qpe.CapturedRun(runner)
+    for rep in range(3):
+        runner.probs[0].fill_(-1.0)
+        host(qpe.run(items[0][0], items[0][1], items[0][2], "mixed"))
+        out = graph()
+        assert np.array_equal(host(out[0]), eager), rep
+    ref = O.qpe_probs(p.U, p.psi, p.n_meas)
+    assert float(np.abs(eager - ref).max()) < 1e-6

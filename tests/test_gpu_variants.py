@@ -1,0 +1,71 @@
+"""Every tile variant of every kernel class against the default variant and
+the oracle, including grids whose last row tile is ragged or whose row count
+is below one tile."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.qpe_oracle as O
+from tests.libutil import ensure_built
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qpe():
+    ensure_built()
+    from paper_2507_17175_amd import qpe as q
+    return q
+
+
+def _run_all_variants(qpe, cls, form, n, t, seed, flags=0):
+    p = make_problem(n, t, np.random.default_rng(seed))
+    U, psi = torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda()
+    ctx = qpe.context(0)
+    out = {}
+    try:
+        for v in range(qpe.kernel_variants(cls) + 1):
+            ctx.set_variant(cls, v)
+            out[v] = qpe.run(U, psi, n, form=form, flags=flags).cpu().numpy()
+    finally:
+        ctx.set_variant(cls, 0)
+    return p, out
+
+
+@pytest.mark.parametrize("n,t", [(10, 5), (10, 6), (9, 7), (8, 8), (5, 7), (3, 8)])
+def test_ctrl_mixed_variants(qpe, n, t):
+    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 100 + n + t)
+    ref = O.qpe_probs(p.U, p.psi, n)
+    for v, P in out.items():
+        assert np.array_equal(P, out[0]), f"variant {v} differs from the default"
+        assert float(np.abs(P - ref).max()) <= 1e-6, v
+
+
+@pytest.mark.parametrize("n,t", [(9, 7), (6, 8)])
+def test_ctrl_mixed_variants_prefix_doubling(qpe, n, t):
+    from paper_2507_17175_amd.qpe import PREFIX_DOUBLING
+    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 200 + n + t, flags=PREFIX_DOUBLING)
+    ref = O.qpe_probs(p.U, p.psi, n)
+    for v, P in out.items():
+        assert np.array_equal(P, out[0]), v
+        assert float(np.abs(P - ref).max()) <= 1e-6, v
+
+
+@pytest.mark.parametrize("n,t", [(8, 5), (9, 7)])
+def test_ctrl_f64_variants(qpe, n, t):
+    p, out = _run_all_variants(qpe, "ctrl_f64", "fp64", n, t, 300 + n + t)
+    ref = O.qpe_probs(p.U, p.psi, n)
+    for v, P in out.items():
+        assert float(np.abs(P - out[0]).max()) <= 1e-13, v
+        assert float(np.abs(P - ref).max()) <= 1e-11, v
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_zgemm_variants(qpe, form):
+    n, t = 9, 7
+    p, out = _run_all_variants(qpe, "zgemm", form, n, t, 400)
+    ref = O.qpe_probs(p.U, p.psi, n)
+    for v, P in out.items():
+        assert float(np.abs(P - out[0]).max()) <= (1e-12 if form == "fp64" else 1e-7), v
+        assert float(np.abs(P - ref).max()) <= (1e-11 if form == "fp64" else 1e-6), v
