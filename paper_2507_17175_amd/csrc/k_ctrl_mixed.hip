@@ -513,6 +513,166 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_tb(float2* __restrict__ buf
   ctrl_tb_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
+// ----------------------------------------------------------------- variant 5
+// Like variant 2 for the state operand, but the operator fragments bypass
+// LDS: each wave loads its own B fragments (for one 32-column block and one
+// plane, lane l needs the 8 K values 8 (l / 32) .. of column l % 32, which in
+// the blocked plane layout are 16 contiguous bytes, so a wave's load covers
+// 1 KB contiguously) straight into registers one slab ahead. This halves the
+// LDS stores per slab at the price of reading each operator fragment from L2
+// once per wave row (WM times) instead of once per workgroup.
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ctrl_bg_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                             const uint16_t* __restrict__ planes, int n, int t, int k,
+                                             uint64_t pmask, int tile_m, int tile_n) {
+  constexpr int NT = 512;
+  static_assert(WM * WN == 8, "8 waves");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KS = 16;   // complex K per slab
+  constexpr int ROW = 24;  // padded LDS row in bf16 (48 bytes)
+  constexpr int A_PLANE = BM * ROW;
+  constexpr int BUF = 6 * A_PLANE;
+  constexpr int CA = BM * KS / 4 / NT;
+  static_assert(CA >= 1 && CA * NT * 4 == BM * KS, "tile/thread mismatch");
+
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+  const int lr = lane & 31, ko = (lane >> 5) * 8;
+
+  const float2* src_row[CA];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int c = tid + q * NT;
+    int gi = min(i0 + c / 4, M - 1);
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+  }
+  // operator fragment base of this lane: column j0 + wj0 + 32 y + lr
+  const uint16_t* bsrc = planes + int64_t(j0 + wj0 + lr) * kPlaneBlock + ko;
+
+  float4 ra[CA][2];
+  auto load_a = [&](int s) {
+    const int k0 = s * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[q][0] = p[0];
+      ra[q][1] = p[1];
+    }
+  };
+  bf16x8 bset[2][FN][6];
+  auto load_b = [&](auto setc, int s) {
+    constexpr int S = decltype(setc)::value;
+    const uint16_t* p0 = bsrc + int64_t(s) * d * kPlaneBlock;
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bset[S][y][pl] = *reinterpret_cast<const bf16x8*>(p0 + pl * dd + 32 * y * kPlaneBlock);
+  };
+  bf16x4 pc[CA][6];
+  auto split_part = [&](int u) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4 w = ra[q][u >> 1];
+      __bf16 h, m, l;
+      split3((u & 1) ? w.z : w.x, h, m, l);
+      pc[q][0][u] = h;
+      pc[q][2][u] = m;
+      pc[q][4][u] = l;
+      split3((u & 1) ? w.w : w.y, h, m, l);
+      pc[q][1][u] = h;
+      pc[q][3][u] = m;
+      pc[q][5][u] = l;
+    }
+  };
+  auto write_a = [&](int b) {
+    uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tid + q * NT;
+      int r = c / 4, kq = c & 3;
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[x][y][v] = 0.f;
+        acc_im[x][y][v] = 0.f;
+      }
+
+  using Set0 = std::integral_constant<int, 0>;
+  using Set1 = std::integral_constant<int, 1>;
+  const int nk = d / KS;  // a power of two >= 2
+  load_a(0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_part(u);
+  write_a(0);
+  load_a(min(1, nk - 1));
+  load_b(Set0{}, 0);
+  __syncthreads();
+
+  // slab s: operator fragments from register set s & 1 (loaded during slab
+  // s - 1), state fragments from LDS buffer s & 1; the next slab's operator
+  // fragments go to the other set, its state slab to the other buffer.
+  auto slab = [&](auto setc, int s) {
+    constexpr int S = decltype(setc)::value;
+    constexpr int SN = 1 - S;
+    const uint16_t* base = lds + S * BUF;
+    bf16x8 av[FM][6], bneg[FN][3];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pc2 = 0; pc2 < 3; ++pc2) bneg[y][pc2] = negate(bset[S][y][2 * pc2 + 1]);
+    load_b(std::integral_constant<int, SN>{}, min(s + 1, nk - 1));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      mma_pair<FM, FN>(c, acc_re, acc_im, av, bset[S], bneg);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < 4) split_part(c);
+      if (c == 3) write_a(SN);
+      if (c == 5) load_a(min(s + 2, nk - 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+  };
+  for (int s = 0; s < nk; s += 2) {
+    slab(Set0{}, s);
+    slab(Set1{}, s + 1);
+  }
+
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_bg(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_bg_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
 // ----------------------------------------------------------------- variant 1
 template <int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
@@ -717,13 +877,20 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 4; }
+int ctrl_mixed_variants() { return 5; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant) {
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (variant == 5) {
+    // operator fragments straight from L2 into registers
+    if (t >= 7) return launch<512>(k_ctrl_bf16x6_bg<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6) return launch<512>(k_ctrl_bf16x6_bg<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }
