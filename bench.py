@@ -64,6 +64,7 @@ CONFIGS = {
     "c2": "qpe-n16-t10 (Haar 1024x1024, uniform eigenphase, eigenvector input)",
     "c3": "qpe-n20-t8 (Haar 256x256, 3 eigenphases within 2^-18, superposed eigenvectors)",
     "c4": "qpe-batch-512 (512 instances, t uniform in 3..8, n uniform in 8..16, Haar, eigenvector inputs)",
+    "c5": "qpe-n18-t14 (Haar 16384x16384, uniform eigenphase, eigenvector input; 2^32 amplitudes)",
 }
 
 
@@ -118,11 +119,62 @@ def bench_batch(a, qpe, torch, config_problems):
     return 0
 
 
+def bench_c5(a, qpe, torch):
+    """The VRAM-scale workload (2^32 amplitudes, 32 GiB complex64 state,
+    ~80 GiB of workspace): one mixed-form circuit takes tens of seconds, so
+    it runs --steps circuits (default 1) without the autotuner, the FP64 form
+    or the CPU oracle, plus one prefix-doubling circuit."""
+    from workloads import config5_device
+
+    t0 = time.perf_counter()
+    U, psi, phi0, n, t = config5_device()
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print(json.dumps({"progress": "c5 inputs generated", "seconds": round(gen_s, 1)}), file=sys.stderr, flush=True)
+    N, d = 1 << n, 1 << t
+    prob = {"U": U, "psi": psi, "n": n}
+    steps = a.steps
+    el, timing, rep, P = time_form(qpe, torch, prob, "mixed", steps, a.warmup)
+    print(json.dumps({"progress": "c5 gate route timed", "seconds": round(el, 1)}), file=sys.stderr, flush=True)
+    flops_per_launch = 8.0 * (N // 2) * d * d
+    g_cnt, g_ms = timing["ctrl_gemm"]
+    avg_s = (g_ms / g_cnt) / 1e3
+    achieved = flops_per_launch / avg_s / 1e12
+    el_d, timing_d, rep_d, P_dbl = time_form(qpe, torch, prob, "mixed", 1, 0, flags=qpe.PREFIX_DOUBLING)
+    out = {
+        "metric": "QPE circuits/s (mixed form)",
+        "value": round(steps / el, 5), "unit": "circuits/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * el / steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
+        "data": "synthetic (seeded Haar unitary generated on the device, eigenvector input)",
+        "config": {"workload": CONFIGS["c5"], "n_meas": n, "n_mat": t, "amplitudes": N * d, "form": "mixed",
+                   "workspace_bytes": qpe.workspace_bytes([(n, t)], "mixed")},
+        "roofline": {"kernel": "k_ctrl_bf16x6 (controlled product, split-BF16 x6 on MFMA)", "bound": "mfma",
+                     "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                     "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
+                     "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 3),
+                     "launches": g_cnt, "traffic": None},
+        "breakdown_mixed": {k: {"launches": c, "ms_per_circuit": round(ms / steps, 2)} for k, (c, ms) in timing.items()},
+        "report_mixed": {"prob_sum": float(rep["prob_sum"]), "unitarity_defect": float(rep["unitarity_defect"]),
+                         "flags": int(rep["flags"])},
+        "prefix_doubling_form": {"seconds_per_circuit": round(el_d, 2),
+                                 "bitwise_equal_to_gate_route": bool(np.array_equal(P_dbl, P)),
+                                 "breakdown": {k: {"launches": c, "ms_per_circuit": round(ms, 2)}
+                                               for k, (c, ms) in timing_d.items()}},
+        "input_generation_seconds": round(gen_s, 1),
+        "target_phase": phi0,
+        "argmax_outcome": int(np.argmax(P)),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed circuits (default 20; 1 for c5)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed circuits first (default 3; 0 for c5)")
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -272,6 +324,10 @@ def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
 
 def main():
     a = parse()
+    if a.steps is None:
+        a.steps = 1 if a.config == "c5" else 20
+    if a.warmup is None:
+        a.warmup = 0 if a.config == "c5" else 3
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
@@ -290,6 +346,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     if a.config == "c4":
         return bench_batch(a, qpe, torch, config_problems)
+    if a.config == "c5":
+        return bench_c5(a, qpe, torch)
     p = config_problems(a.config)[0]
     n, t = p.n_meas, p.n_mat
     N, d = 1 << n, 1 << t

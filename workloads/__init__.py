@@ -33,6 +33,7 @@ __all__ = [
     "CONFIG_NAMES",
     "analytic_problem",
     "eigenbasis_problems",
+    "config5_device",
 ]
 
 
@@ -178,6 +179,37 @@ def eigenbasis_problems(n_meas: int, n_mat: int = 4, seed: int = 12) -> List[Pro
     return [Problem(n_meas, n_mat, U, np.ascontiguousarray(q[:, i].copy()), phis=phis,
                     coeff_idx=np.array([i]), coeffs=np.array([1.0 + 0j]), Q=q,
                     label=f"eigenbasis-n{n_meas}-t{n_mat}-i{i}") for i in range(d)]
+
+
+def config5_device(seed: int = 5, device: str = "cuda"):
+    """The VRAM-scale workload: N_meas = 18, N_mat = 14 (2^32 amplitudes), a
+    16384 x 16384 Haar unitary with a uniform target eigenphase and its
+    eigenvector as input. The Gaussians are drawn on the host in the usual
+    order (A, then B, then the phases); the QR factorisation and U = Q
+    diag(exp(2 pi i phi)) Q^H run on the device with torch, because on the
+    host they take many minutes. Returns (U, psi, phi_0, n_meas, n_mat) with
+    U and psi complex128 device tensors."""
+    import torch
+
+    n, t = 18, 14
+    d = 1 << t
+    rng = np.random.default_rng(seed)
+    a = torch.from_numpy(rng.standard_normal((d, d))).to(device)
+    b = torch.from_numpy(rng.standard_normal((d, d))).to(device)
+    z = torch.complex(a, b) / np.sqrt(2.0)
+    del a, b
+    q, r = torch.linalg.qr(z)
+    del z
+    diag = torch.diagonal(r)
+    q = q * (diag / diag.abs())[None, :]
+    del r
+    phi0 = float(rng.random())
+    phis = np.concatenate([[phi0], rng.random(d - 1)])
+    lam = torch.exp(2j * np.pi * torch.from_numpy(phis).to(device))
+    U = ((q * lam[None, :]) @ q.conj().T).contiguous()
+    psi = q[:, 0].contiguous().clone()
+    del q
+    return U, psi, phi0, n, t
 
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4")
