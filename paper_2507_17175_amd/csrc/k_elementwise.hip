@@ -116,16 +116,21 @@ __device__ inline double nan_max(double a, double b) { return (b > a || b != b) 
 // defect = max(defect, max |G_ij|). The max of non-negative doubles is
 // order-independent, so the atomic on the IEEE bit pattern (monotone for
 // non-negative values) is deterministic.
-__device__ inline void subi_range(double2* __restrict__ G, int d, int64_t e0, int64_t e1, int64_t stride,
-                                  unsigned long long* __restrict__ defect_bits) {
+__device__ inline void subi_range(double2* __restrict__ G, const double2* __restrict__ G2, int d, int64_t e0,
+                                  int64_t e1, int64_t stride, unsigned long long* __restrict__ defect_bits) {
   __shared__ double red[kThreads / 64];
   double mx = 0.0;
   for (int64_t e = e0; e < e1; e += stride) {
     double2 g = G[e];
-    if ((e / d) == (e % d)) {
-      g.x -= 1.0;
-      G[e] = g;
+    const bool diag = (e / d) == (e % d);
+    if (G2) {
+      // the two K halves of a split Gram product, added in a fixed order
+      const double2 h = G2[e];
+      g.x += h.x;
+      g.y += h.y;
     }
+    if (diag) g.x -= 1.0;
+    if (G2 || diag) G[e] = g;
     mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
   }
   for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
@@ -273,9 +278,10 @@ __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __rest
     split_entry(V, planes, t, e);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G, int d,
+__global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G,
+                                                                  const double2* __restrict__ G2, int d,
                                                                   unsigned long long* __restrict__ defect_bits) {
-  subi_range(G, d, blockIdx.x * int64_t(kThreads) + threadIdx.x, int64_t(d) * d, int64_t(gridDim.x) * kThreads,
+  subi_range(G, G2, d, blockIdx.x * int64_t(kThreads) + threadIdx.x, int64_t(d) * d, int64_t(gridDim.x) * kThreads,
              defect_bits);
 }
 
@@ -446,7 +452,9 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
     }
     case BK_SUBI: {
       int64_t e0 = local * kSubiTile, e1 = min(e0 + int64_t(kSubiTile), int64_t(d) * d);
-      subi_range(reinterpret_cast<double2*>(D.ws + L.gbuf), d, e0 + threadIdx.x, e1, kThreads, defect);
+      subi_range(reinterpret_cast<double2*>(D.ws + L.gbuf),
+                 gram_split(t) ? reinterpret_cast<const double2*>(D.ws + L.gbuf2) : nullptr, d, e0 + threadIdx.x,
+                 e1, kThreads, defect);
       break;
     }
     case BK_NSPREP:
@@ -549,9 +557,10 @@ hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_sub_identity_defect(double2* G, int d, unsigned long long* defect_bits, hipStream_t s) {
+hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
+                                      hipStream_t s) {
   int64_t dd = int64_t(d) * d;
-  hipLaunchKernelGGL(k_sub_identity_defect, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, G, d,
+  hipLaunchKernelGGL(k_sub_identity_defect, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, G, G2, d,
                      defect_bits);
   return hipGetLastError();
 }

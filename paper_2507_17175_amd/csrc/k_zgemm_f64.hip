@@ -39,12 +39,13 @@ __device__ inline double2* pick(const GatherArgs& g, int which) {
   return reinterpret_cast<double2*>(b0 + (which ? delta : uintptr_t(0)));
 }
 
-__device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
+__device__ inline int2 xcd_tile_of(int w, int tiles_m, int tiles_n) {
   const int total = tiles_m * tiles_n;
-  int w = blockIdx.x;
   if ((total & 7) == 0) w = (w & 7) * (total >> 3) + (w >> 3);
   return make_int2(w / tiles_n, w % tiles_n);
 }
+
+__device__ inline int2 xcd_tile(int tiles_m, int tiles_n) { return xcd_tile_of(blockIdx.x, tiles_m, tiles_n); }
 
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs& g, int tile_m, int tile_n) {
@@ -252,10 +253,30 @@ __device__ inline int2 upper_tile(int w, int T) {
   return make_int2(tm, tm + w);
 }
 
+// Second K half of a split product: the operands start K/2 further along K
+// and the result goes to C2.
+template <int OPA, int OPB>
+__device__ inline void to_second_half(ZgemmArgs& a) {
+  const int kh = a.K / 2;
+  a.A += OPA == OP_N ? int64_t(kh) : int64_t(kh) * a.lda;
+  a.B += OPB == OP_N ? int64_t(kh) * a.ldb : int64_t(kh);
+  a.C = a.C2;
+}
+
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
   const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
-  const int2 tile = a.herm ? upper_tile(blockIdx.x, tiles_m) : xcd_tile(tiles_m, tiles_n);
+  int w = blockIdx.x;
+  if (a.C2) {
+    // split K: workgroups [0, tiles) take the first half, the rest the second
+    const int tiles = a.herm ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+    if (w >= tiles) {
+      w -= tiles;
+      to_second_half<OPA, OPB>(a);
+    }
+    a.K /= 2;
+  }
+  const int2 tile = a.herm ? upper_tile(w, tiles_m) : xcd_tile_of(w, tiles_m, tiles_n);
   zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN>(a, g, tile.x, tile.y);
 }
 
@@ -304,7 +325,19 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
   GatherArgs g{};
   if (KIND == BK_GRAM) {
     a.herm = 1;
-    const int2 tile = upper_tile(int(local), tiles_n);
+    int w = int(local);
+    if (gram_split(D.t)) {
+      // the two K halves as in the single-instance path: tiles [0, U) take
+      // the first half into gbuf, [U, 2U) the second into gbuf2
+      const int upper = tiles_n * (tiles_n + 1) / 2;
+      a.C2 = reinterpret_cast<double2*>(D.ws + L.gbuf2);
+      if (w >= upper) {
+        w -= upper;
+        to_second_half<OPA, OP_N>(a);
+      }
+      a.K /= 2;
+    }
+    const int2 tile = upper_tile(w, tiles_n);
     zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, tile.x, tile.y);
   } else {
     zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
@@ -341,6 +374,7 @@ hipError_t go(const ZgemmArgs& a_in, const GatherArgs& g, hipStream_t s) {
   if (a.herm && (BM != BN || a.M != a.N)) a.herm = 0;
   const int T = (a.M + BM - 1) / BM;
   int tiles = a.herm ? T * (T + 1) / 2 : T * ((a.N + BN - 1) / BN);
+  if (a.C2) tiles *= 2;  // both K halves
   hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
   return hipGetLastError();
 }

@@ -221,7 +221,8 @@ struct TimerScope {
 // product's error is O(1e-7 defect), far below the FP64 rounding of X),
 // accumulated in FP32 into g, which E no longer needs by then.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
-                            bool polar, unsigned long long* defect, uint16_t* planes = nullptr) {
+                            bool polar, unsigned long long* defect, uint16_t* planes = nullptr,
+                            double2* g2 = nullptr) {
   hipStream_t s = ctx->stream;
   const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
@@ -241,8 +242,9 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   h.B = sq;
   h.C = g;
   h.herm = 1;
+  h.C2 = gram_split(tz) ? g2 : nullptr;  // two K halves into g and g2
   QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // G = X^H X
-  QPE_HIP(ctx, launch_sub_identity_defect(g, d, defect, s));
+  QPE_HIP(ctx, launch_sub_identity_defect(g, h.C2, d, defect, s));
   if (planes && tz >= 5) {
     float2* x32 = reinterpret_cast<float2*>(out);
     float2* xe = reinterpret_cast<float2*>(g);
@@ -316,6 +318,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   double2* A = reinterpret_cast<double2*>(ws + L.vbuf);
   double2* B = reinterpret_cast<double2*>(ws + L.tbuf);
   double2* G = polar ? reinterpret_cast<double2*>(ws + L.gbuf) : nullptr;
+  double2* G2 = (polar && gram_split(t)) ? reinterpret_cast<double2*>(ws + L.gbuf2) : nullptr;
   uint16_t* planes = (mixed && t >= 5) ? reinterpret_cast<uint16_t*>(ws + L.planes) : nullptr;
   unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + L.scratch);
   const double2* psi = static_cast<const double2*>(p.psi);
@@ -335,7 +338,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2);
       if (st != QPE_OK) return st;
       cur = polar ? other : sq;
     }
@@ -706,7 +709,7 @@ QPE_API qpe_status qpe_powers_workspace_size(int n_mat, size_t* bytes) {
   if (!bytes) return QPE_ERR_ARG;
   if (n_mat < 0 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
   size_t mat = (size_t(1) << (2 * n_mat)) * 16;
-  *bytes = 2 * align_up(mat) + align_up(64);
+  *bytes = (gram_split(n_mat) ? 3 : 2) * align_up(mat) + align_up(64);
   return QPE_OK;
 }
 
@@ -728,7 +731,9 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
   char* ws = static_cast<char*>(workspace);
   double2* sq = reinterpret_cast<double2*>(ws);
   double2* g = reinterpret_cast<double2*>(ws + align_up(mat * 16));
-  unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + 2 * align_up(mat * 16));
+  double2* g2 = gram_split(n_mat) ? reinterpret_cast<double2*>(ws + 2 * align_up(mat * 16)) : nullptr;
+  unsigned long long* defect =
+      reinterpret_cast<unsigned long long*>(ws + (gram_split(n_mat) ? 3 : 2) * align_up(mat * 16));
   double2* V = static_cast<double2*>(V_out);
   const bool polar = !(flags & QPE_NO_POLAR);
   QPE_HIP(ctx, launch_zero_u64(defect, 1, ctx->stream));
@@ -736,7 +741,7 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
   for (int k = 1; k < count_k; ++k) {
     const double2* cur = V + (k - 1) * mat;
     double2* out = V + k * mat;
-    s = square_and_polar(ctx, d, cur, polar ? sq : out, g, out, polar, defect);
+    s = square_and_polar(ctx, d, cur, polar ? sq : out, g, out, polar, defect, nullptr, g2);
     if (s != QPE_OK) return s;
   }
   if (report) {

@@ -85,9 +85,18 @@ constexpr size_t kAlign = 256;
 __host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 __host__ __device__ inline int tw_split(int n) { return (n + 1) / 2; }
 
+// The Gram product X^H X of the Newton-Schulz step computes only its upper
+// tiles. At d = 1024 and 2048 their count (528 tiles of 32 x 32, or of
+// 64 x 64) leaves the 256 CUs unevenly loaded (two or three workgroups
+// each), so the product is split in two K halves (each tile twice) whose
+// partial sums go to gbuf and gbuf2 and are added, in that order, by the
+// identity subtraction (measured at d = 1024: 137 us -> 108 us). The batched
+// path splits at the same sizes, so both paths add the same partial sums.
+__host__ __device__ inline bool gram_split(int t) { return t == 10 || t == 11; }
+
 // Regions of one instance's workspace (byte offsets from its base).
 struct RunLayout {
-  size_t state0, state1, vbuf, tbuf, gbuf, planes, tw_hi, tw_lo, scratch, total;
+  size_t state0, state1, vbuf, tbuf, gbuf, gbuf2, planes, tw_hi, tw_lo, scratch, total;
 };
 
 __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool polar) {
@@ -106,6 +115,8 @@ __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool p
   off = align_up(off + mat);
   L.gbuf = off;
   if (polar) off = align_up(off + mat);
+  L.gbuf2 = off;
+  if (polar && gram_split(t)) off = align_up(off + mat);
   L.planes = off;
   if (mixed && t >= 5) off = align_up(off + 6 * d * d * 2);
   const int h = tw_split(n);
@@ -200,9 +211,9 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     case BK_SQ:
       return (step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
     case BK_GRAM: {
-      // Hermitian: the tiles on or above the diagonal
+      // Hermitian: the tiles on or above the diagonal (twice when split)
       const int64_t T = cdiv(d, kBatchGemmTile);
-      return (polar && step >= 1 && step < n) ? T * (T + 1) / 2 : 0;
+      return (polar && step >= 1 && step < n) ? T * (T + 1) / 2 * (gram_split(t) ? 2 : 1) : 0;
     }
     case BK_CORR:
       return (polar && !(mixed && t >= 5) && step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile)
@@ -293,7 +304,9 @@ hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStr
 // split(conj(E)); then out = X - XE / 2 (XE = X32 E from the mixed kernel).
 hipError_t launch_ns_prep(const double2* X, const double2* E, float2* X32, uint16_t* planes, int t, hipStream_t s);
 hipError_t launch_ns_update(const double2* X, const float2* XE, double2* out, int t, hipStream_t s);
-hipError_t launch_sub_identity_defect(double2* G, int d, unsigned long long* defect_bits, hipStream_t s);
+// G <- G (+ G2 when not null) - I, and the defect max |G_ij| (atomic max).
+hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
+                                      hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
                        hipStream_t s);
@@ -328,6 +341,9 @@ struct ZgemmArgs {
   // Hermitian result (op(A) = B^H, alpha real, beta 0): only tiles on or
   // above the diagonal are computed; each mirrors itself below it.
   int herm;
+  // K split in two halves (beta 0): the first half's product goes to C, the
+  // second's to C2 (both M x N with ldc); the caller adds them.
+  double2* C2;
 };
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant);
 int zgemm_variants();
