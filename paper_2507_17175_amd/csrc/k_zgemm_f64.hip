@@ -156,13 +156,18 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
     }
   };
 
-  f64x4 acc_re[FM][FN], acc_im[FM][FN];
+  // Three real products per complex product (Gauss): with a = ar + i ai and
+  // b = br + i bi, t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi),
+  // then re = t1 - t2 and im = t3 - t1 - t2 (normwise as accurate as the
+  // four-product form, within a small constant factor).
+  f64x4 acc_t1[FM][FN], acc_t2[FM][FN], acc_t3[FM][FN];
 #pragma unroll
   for (int x = 0; x < FM; ++x)
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
-      acc_re[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-      acc_im[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc_t1[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc_t2[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc_t3[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
 
   const int nk = (a.K + kBK - 1) / kBK;
@@ -182,23 +187,24 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
     for (int k4 = 0; k4 < kBK / 4; ++k4) {
       const int kr = k4 * 4 + lk;
       double2 av[FM], bv[FN];
+      double as[FM], bs[FN];
 #pragma unroll
-      for (int x = 0; x < FM; ++x) av[x] = As[kr * PA + wi0 + x * 16 + lr];
+      for (int x = 0; x < FM; ++x) {
+        av[x] = As[kr * PA + wi0 + x * 16 + lr];
+        as[x] = av[x].x + av[x].y;
+      }
 #pragma unroll
-      for (int y = 0; y < FN; ++y) bv[y] = Bs[kr * PB + wj0 + y * 16 + lr];
+      for (int y = 0; y < FN; ++y) {
+        bv[y] = Bs[kr * PB + wj0 + y * 16 + lr];
+        bs[y] = bv[y].x + bv[y].y;
+      }
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
         for (int y = 0; y < FN; ++y) {
-          acc_re[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].x, bv[y].x, acc_re[x][y], 0, 0, 0);
-          acc_im[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].x, bv[y].y, acc_im[x][y], 0, 0, 0);
-        }
-#pragma unroll
-      for (int x = 0; x < FM; ++x)
-#pragma unroll
-        for (int y = 0; y < FN; ++y) {
-          acc_re[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[x].y, bv[y].y, acc_re[x][y], 0, 0, 0);
-          acc_im[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].y, bv[y].x, acc_im[x][y], 0, 0, 0);
+          acc_t1[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].x, bv[y].x, acc_t1[x][y], 0, 0, 0);
+          acc_t2[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x].y, bv[y].y, acc_t2[x][y], 0, 0, 0);
+          acc_t3[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[x], bs[y], acc_t3[x][y], 0, 0, 0);
         }
     }
     __syncthreads();
@@ -220,7 +226,8 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
         int gi = i0 + wi0 + x * 16 + 4 * v + lk;
         int gj = j0 + wj0 + y * 16 + lr;
         if (gi >= a.M || gj >= a.N) continue;
-        double re = acc_re[x][y][v], im = acc_im[x][y][v];
+        const double t1 = acc_t1[x][y][v], t2 = acc_t2[x][y][v];
+        double re = t1 - t2, im = acc_t3[x][y][v] - t1 - t2;
         if (GATHER) {
           int64_t j = step_row(gi, g.k, g.pmask);
           double2* dst = pick(g, 1 - src_buffer(j, g.pmask));
@@ -410,7 +417,7 @@ hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
 }  // namespace
 
 int zgemm_variants() { return 5; }
-int ctrl_f64_variants() { return 3; }
+int ctrl_f64_variants() { return 2; }
 
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant) {
   switch (opA * 3 + opB) {
@@ -427,8 +434,10 @@ hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int
   return hipErrorInvalidValue;
 }
 
-// Controlled step variants: 1: 64x64, 4 waves; 2: 128x64, 8 waves;
-// 3: 128x128, 8 waves. Small sizes fall back to 32x32 tiles.
+// Controlled step variants: 1: 64x64, 4 waves; 2: 128x64, 8 waves (the
+// default: with three accumulator sets per tile the 4-wave variant needs 280
+// VGPRs and runs one wave per SIMD: 3.4 ms vs 4.8 ms per c2 step). Small
+// sizes fall back to 32x32 tiles.
 hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n, int t, int k, uint64_t pmask,
                            hipStream_t s, int variant) {
   const int d = 1 << t;
@@ -442,12 +451,10 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
   a.ldc = d;
   GatherArgs g{buf0, buf1, k, pmask};
   if (a.M < 128 || d < 64) return go<OP_N, OP_T, true, 32, 32, 2, 2>(a, g, s);
-  if (variant == 0) variant = 1;
-  if (variant == 3 && d < 128) variant = 2;
+  if (variant == 0) variant = 2;
   switch (variant) {
     case 1: return go<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, s);
     case 2: return go<OP_N, OP_T, true, 128, 64, 4, 2>(a, g, s);
-    case 3: return go<OP_N, OP_T, true, 128, 128, 2, 4>(a, g, s);
   }
   return hipErrorInvalidValue;
 }
