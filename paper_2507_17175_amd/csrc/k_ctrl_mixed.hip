@@ -64,14 +64,17 @@ __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
 
 // Six MFMA products of one (row block, column block) pair for one K chunk of
 // 16: piece pairs with index sum <= 2, four real products per complex one.
-template <int FM, int FN>
+// C0 = 3 keeps only the pairs hm, mh, hh (index sum <= 1, relative error
+// ~2^-16): enough for the Newton-Schulz product X E, whose size is that of
+// the unitarity defect (~1e-15), so its error stays ~1e-20 absolute.
+template <int FM, int FN, int C0 = 0>
 __device__ __forceinline__ void mma_bf16x6(f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
                                            const bf16x8 (&av)[FM][6], const bf16x8 (&bv)[FN][6],
                                            const bf16x8 (&bneg)[FN][3]) {
   constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
   constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
+  for (int c = C0; c < 6; ++c) {
     const int pa = PA[c], pb = PB[c];
 #pragma unroll
     for (int x = 0; x < FM; ++x)
@@ -135,7 +138,7 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const
 }
 
 // ----------------------------------------------------------------- variant 2
-template <int BM, int BN, int WM, int WN, bool IL = true>
+template <int BM, int BN, int WM, int WN, bool IL = true, int C0 = 0>
 __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                              const uint16_t* __restrict__ planes, int n, int t, int k,
                                              uint64_t pmask, int tile_m, int tile_n) {
@@ -286,7 +289,7 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       // instead of after the last MFMA of the slab.
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+        if (c >= C0) mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
         __builtin_amdgcn_sched_barrier(0);
         if (c < 4) split_part(c);
         if (c == 3) write_a(nb);
@@ -295,7 +298,7 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
-      mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+      mma_bf16x6<FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
       store_lds(nb);
       load_global(ns);
     }
@@ -305,13 +308,13 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
-template <int BM, int BN, int WM, int WN, bool IL = true>
+template <int BM, int BN, int WM, int WN, bool IL = true, int C0 = 0>
 __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                          const uint16_t* __restrict__ planes, int n, int t, int k,
                                                          uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_db_tile<BM, BN, WM, WN, IL>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_db_tile<BM, BN, WM, WN, IL, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -674,7 +677,7 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_bg(float2* __restrict__ buf
 }
 
 // ----------------------------------------------------------------- variant 1
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int C0 = 0>
 __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                              const uint16_t* __restrict__ planes, int n, int t, int k,
                                              uint64_t pmask, int tile_m, int tile_n) {
@@ -800,7 +803,7 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
 #pragma unroll
         for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
       }
-      mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+      mma_bf16x6<FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -812,13 +815,13 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int C0 = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
               int k, uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_v1_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_v1_tile<BM, BN, WM, WN, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
 // Grouped controlled step k over the instances of a launch table; the tile
@@ -858,12 +861,13 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
   const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
   const int tiles_n = (1 << D.t) / BN;
   const int tm = int(local / tiles_n), tn = int(local % tiles_n);
+  constexpr int C0 = NS ? 3 : 0;  // the Newton-Schulz product needs three piece pairs
   if constexpr (BN == 32)
-    ctrl_v1_tile<128, 32, 4, 1>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_v1_tile<128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else if constexpr (BN == 64)
-    ctrl_db_tile<128, 64, 4, 2>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_db_tile<128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else
-    ctrl_db_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_db_tile<128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
 }
 
 template <int NT, typename K>
@@ -918,6 +922,22 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
   if (t >= 7) return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ns_product(float2* x32, float2* xe, const uint16_t* planes, int t, hipStream_t s) {
+  // rows [0, d) of x32 times the planes, into rows [0, d) of xe: the
+  // prefix-doubling mapping of a (t + 1)-qubit register
+  const int n = t + 1;
+  const uint64_t pmask = kDoubling;
+  const int64_t big_tiles = (int64_t(1) << t) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
+  if (t >= 6 && big_tiles < 256)
+    return launch<256>(k_ctrl_bf16x6<64, 64, 2, 2, 3>, 64, 64, x32, xe, planes, n, t, t, pmask, s);
+  if (t >= 7)
+    return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4, true, 3>, 128, 128, x32, xe, planes, n, t, t, pmask, s);
+  if (t == 6)
+    return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2, true, 3>, 128, 64, x32, xe, planes, n, t, t, pmask, s);
+  if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1, 3>, 128, 32, x32, xe, planes, n, t, t, pmask, s);
   return hipErrorInvalidValue;
 }
 

@@ -216,10 +216,10 @@ struct TimerScope {
 // whose E = X^H X - I also yields the unitarity defect max|E_ij|.
 // sq and out are distinct from cur; out may equal the dead predecessor.
 // With planes (the mixed form, d >= 32) the correction X E runs on the
-// split-BF16 controlled-product kernel: X rounded to complex64 (staged in
-// out) times E split into three BF16 pieces (E is O(defect), so the
-// product's error is O(1e-7 defect), far below the FP64 rounding of X),
-// accumulated in FP32 into g, which E no longer needs by then.
+// split-BF16 kernel: X rounded to complex64 (staged in out) times E split
+// into BF16 pieces, three piece pairs (E is O(defect), so the product's
+// error is O(1e-5 defect), far below the FP64 rounding of X), accumulated
+// in FP32 into g, which E no longer needs by then.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
                             bool polar, unsigned long long* defect, uint16_t* planes = nullptr,
                             double2* g2 = nullptr) {
@@ -249,10 +249,7 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
     float2* x32 = reinterpret_cast<float2*>(out);
     float2* xe = reinterpret_cast<float2*>(g);
     QPE_HIP(ctx, launch_ns_prep(sq, g, x32, planes, tz, s));
-    // Prefix-doubling mapping with a (t+1)-qubit register: rows [0, d) of
-    // x32 times E land in rows [0, d) of xe.
-    QPE_HIP(ctx, launch_ctrl_mixed(x32, xe, planes, tz + 1, tz, tz, kDoubling, s,
-                                   ctx->variant[QPE_KERNEL_CTRL_MIXED][tz]));
+    QPE_HIP(ctx, launch_ns_product(x32, xe, planes, tz, s));
     QPE_HIP(ctx, launch_ns_update(sq, xe, out, tz, s));
     return QPE_OK;
   }

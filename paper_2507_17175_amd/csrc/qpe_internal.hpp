@@ -358,6 +358,10 @@ int ctrl_f64_variants();
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
                              uint64_t pmask, hipStream_t s, int variant);
 int ctrl_mixed_variants();
+// The Newton-Schulz product XE = X32 E (d x d) on the split-BF16 kernel with
+// three piece pairs (E is of the size of the unitarity defect), X32 and the
+// planes of conj(E) as written by launch_ns_prep.
+hipError_t launch_ns_product(float2* x32, float2* xe, const uint16_t* planes, int t, hipStream_t s);
 // Controlled step k for d <= 16 on the vector ALUs (both forms).
 hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* V, int n, int t, int k,
                              uint64_t pmask, hipStream_t s);
