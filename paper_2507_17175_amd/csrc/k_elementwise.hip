@@ -87,13 +87,10 @@ __device__ inline uint16_t bf16_rne(double x, double* rounded) {
 // plane the layout is blocked by 16 columns: element (row j, col c) sits at
 // ((c / 16) * d + j) * 16 + c % 16, so that a tile of consecutive rows and 16
 // consecutive columns is contiguous.
-__device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e,
-                                   bool conj = false) {
+__device__ inline void split_value(double2 v, uint16_t* __restrict__ planes, int t, int64_t e) {
   const int64_t d = int64_t(1) << t;
   const int64_t dd = d * d;
   int64_t j = e >> t, c = e & (d - 1);
-  double2 v = V[e];
-  if (conj) v.y = -v.y;
   int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
   double w[2] = {v.x, v.y};
 #pragma unroll
@@ -110,15 +107,34 @@ __device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __re
   }
 }
 
+__device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e,
+                                   bool conj = false) {
+  double2 v = V[e];
+  if (conj) v.y = -v.y;
+  split_value(v, planes, t, e);
+}
+
 __device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 
 // Newton-Schulz support: G <- G - I over elements [e0, e1) (stride), then
 // defect = max(defect, max |G_ij|). The max of non-negative doubles is
 // order-independent, so the atomic on the IEEE bit pattern (monotone for
 // non-negative values) is deterministic.
+// Block-wide max of the threads' mx into *defect_bits (every thread calls).
+__device__ inline void block_max_to(double mx, unsigned long long* __restrict__ defect_bits) {
+  __shared__ double red[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) mx = nan_max(mx, red[w]);
+    if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
+    atomicMax(defect_bits, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
 __device__ inline void subi_range(double2* __restrict__ G, const double2* __restrict__ G2, int d, int64_t e0,
                                   int64_t e1, int64_t stride, unsigned long long* __restrict__ defect_bits) {
-  __shared__ double red[kThreads / 64];
   double mx = 0.0;
   for (int64_t e = e0; e < e1; e += stride) {
     double2 g = G[e];
@@ -133,14 +149,7 @@ __device__ inline void subi_range(double2* __restrict__ G, const double2* __rest
     if (G2 || diag) G[e] = g;
     mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
   }
-  for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / 64; ++w) mx = nan_max(mx, red[w]);
-    if (mx != mx) mx = __longlong_as_double(0x7ff0000000000000ll);  // NaN -> +inf
-    atomicMax(defect_bits, (unsigned long long)__double_as_longlong(mx));
-  }
+  block_max_to(mx, defect_bits);
 }
 
 // Readout rows: P(m(p)) = 2^-n sum_r |X[p][r]|^2 in FP64 (components widened
@@ -239,10 +248,11 @@ __global__ void __launch_bounds__(kThreads) k_twiddles(double2* __restrict__ tw_
 }
 
 // Newton-Schulz correction X E in split BF16 (E = X^H X - I is ~1e-15, so
-// X rounded to FP32 and E split into three BF16 pieces give X E to ~1e-22):
-// X32 = complex64(X), and planes = split(conj(E)) = split(E^T) (E is
-// Hermitian), so that the controlled-product kernel's row x V^T with
-// V = conj(E) computes row x E.
+// X rounded to FP32 times E in BF16 pieces, three piece pairs, gives X E to
+// ~1e-20): X32 = complex64(X), and planes = split(conj(E)) = split(E^T) (E
+// is Hermitian), so that the controlled-product kernel's row x V^T with
+// V = conj(E) computes row x E. These per-element bodies serve the batched
+// path; the single-instance path runs the fused kernels below.
 __device__ inline void ns_prep_entry(const double2* __restrict__ X, const double2* __restrict__ E,
                                      float2* __restrict__ X32, uint16_t* __restrict__ planes, int t, int64_t e) {
   double2 x = X[e];
@@ -258,17 +268,47 @@ __device__ inline void ns_update_entry(const double2* __restrict__ X, const floa
   out[e] = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
 }
 
-__global__ void __launch_bounds__(kThreads) k_ns_prep(const double2* __restrict__ X, const double2* __restrict__ E,
-                                                      float2* __restrict__ X32, uint16_t* __restrict__ planes, int t) {
-  const int64_t dd = int64_t(1) << (2 * t);
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
-    ns_prep_entry(X, E, X32, planes, t, e);
+
+// Mixed-form Newton-Schulz preparation in one pass: E = G (+ G2) - I with the
+// defect max |E_ij|, X32 = complex64(X), planes = split(conj(E)). E itself
+// is not stored (only its planes are used).
+__global__ void __launch_bounds__(kThreads) k_ns_prep_fused(const double2* __restrict__ X,
+                                                            const double2* __restrict__ G,
+                                                            const double2* __restrict__ G2, float2* __restrict__ X32,
+                                                            uint16_t* __restrict__ planes, int t,
+                                                            unsigned long long* __restrict__ defect_bits) {
+  const int64_t d = int64_t(1) << t, dd = d * d;
+  double mx = 0.0;
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+    double2 g = G[e];
+    if (G2) {
+      const double2 h = G2[e];
+      g.x += h.x;
+      g.y += h.y;
+    }
+    if ((e >> t) == (e & (d - 1))) g.x -= 1.0;
+    mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
+    const double2 x = X[e];
+    X32[e] = make_float2(float(x.x), float(x.y));
+    split_value(make_double2(g.x, -g.y), planes, t, e);
+  }
+  block_max_to(mx, defect_bits);
 }
 
-__global__ void __launch_bounds__(kThreads) k_ns_update(const double2* __restrict__ X, const float2* __restrict__ XE,
-                                                        double2* __restrict__ out, int64_t dd) {
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
-    ns_update_entry(X, XE, out, e);
+// The Newton-Schulz update and the operator split of the new power in one
+// pass: out = X - XE / 2, planes = split(out).
+__global__ void __launch_bounds__(kThreads) k_ns_update_split(const double2* __restrict__ X,
+                                                              const float2* __restrict__ XE,
+                                                              double2* __restrict__ out,
+                                                              uint16_t* __restrict__ planes, int t) {
+  const int64_t dd = int64_t(1) << (2 * t);
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+    const double2 x = X[e];
+    const float2 c = XE[e];
+    const double2 o = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
+    out[e] = o;
+    split_value(o, planes, t, e);
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
@@ -539,15 +579,18 @@ hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_ns_prep(const double2* X, const double2* E, float2* X32, uint16_t* planes, int t, hipStream_t s) {
+hipError_t launch_ns_prep_fused(const double2* X, const double2* G, const double2* G2, float2* X32, uint16_t* planes,
+                                int t, unsigned long long* defect_bits, hipStream_t s) {
   int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_ns_prep, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, E, X32, planes, t);
+  hipLaunchKernelGGL(k_ns_prep_fused, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, X, G, G2, X32, planes,
+                     t, defect_bits);
   return hipGetLastError();
 }
 
-hipError_t launch_ns_update(const double2* X, const float2* XE, double2* out, int t, hipStream_t s) {
+hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* out, uint16_t* planes, int t,
+                                  hipStream_t s) {
   int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_ns_update, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, dd);
+  hipLaunchKernelGGL(k_ns_update_split, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
   return hipGetLastError();
 }
 

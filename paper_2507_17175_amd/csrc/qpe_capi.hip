@@ -222,7 +222,7 @@ struct TimerScope {
 // in FP32 into g, which E no longer needs by then.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
                             bool polar, unsigned long long* defect, uint16_t* planes = nullptr,
-                            double2* g2 = nullptr) {
+                            double2* g2 = nullptr, bool* planes_hold_out = nullptr) {
   hipStream_t s = ctx->stream;
   const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
@@ -244,15 +244,19 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   h.herm = 1;
   h.C2 = gram_split(tz) ? g2 : nullptr;  // two K halves into g and g2
   QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // G = X^H X
-  QPE_HIP(ctx, launch_sub_identity_defect(g, h.C2, d, defect, s));
   if (planes && tz >= 5) {
+    // E = G - I with the defect, X -> complex64 and the split of conj(E) in
+    // one pass; after the product, the update also splits the new power
+    // into the planes, which then hold the operator of the next step.
     float2* x32 = reinterpret_cast<float2*>(out);
     float2* xe = reinterpret_cast<float2*>(g);
-    QPE_HIP(ctx, launch_ns_prep(sq, g, x32, planes, tz, s));
+    QPE_HIP(ctx, launch_ns_prep_fused(sq, g, h.C2, x32, planes, tz, defect, s));
     QPE_HIP(ctx, launch_ns_product(x32, xe, planes, tz, s));
-    QPE_HIP(ctx, launch_ns_update(sq, xe, out, tz, s));
+    QPE_HIP(ctx, launch_ns_update_split(sq, xe, out, planes, tz, s));
+    if (planes_hold_out) *planes_hold_out = true;
     return QPE_OK;
   }
+  QPE_HIP(ctx, launch_sub_identity_defect(g, h.C2, d, defect, s));
   ZgemmArgs c = a;
   c.A = sq;
   c.B = g;
@@ -266,13 +270,13 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
 }
 
 qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const double2* V, void* s0, void* s1,
-                      uint16_t* planes, uint64_t pmask) {
+                      uint16_t* planes, uint64_t pmask, bool need_split = true) {
   hipStream_t s = ctx->stream;
   if (t <= 4) {
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
     QPE_HIP(ctx, launch_ctrl_small(mixed, s0, s1, V, n, t, k, pmask, s));
   } else if (mixed) {
-    {
+    if (need_split) {
       TimerScope ts(ctx, QPE_TIMER_SPLIT);
       QPE_HIP(ctx, launch_split_pieces(V, planes, t, s));
     }
@@ -331,11 +335,12 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   }
   const double2* cur = static_cast<const double2*>(p.U);
   for (int k = 0; k < n; ++k) {
+    bool planes_ready = false;  // the Newton-Schulz update already split V_k
     if (k > 0) {
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2, &planes_ready);
       if (st != QPE_OK) return st;
       cur = polar ? other : sq;
     }
@@ -344,9 +349,9 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       // rows [0, 2^k) of s0 -> rows [2^k, 2^(k+1)) of s0: 2^k outputs, as a
       // "register" of k+1 qubits whose second buffer starts at row 2^k.
       char* upper = static_cast<char*>(s0) + (size_t(1) << k) * size_t(d) * amp;
-      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling);
+      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling, !planes_ready);
     } else {
-      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1);
+      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1, !planes_ready);
     }
     if (st != QPE_OK) return st;
   }

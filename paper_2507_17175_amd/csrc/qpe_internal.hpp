@@ -300,10 +300,14 @@ hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, i
                               bool first_row_only = false);
 hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s);
 hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s);
-// Newton-Schulz correction in split BF16: X32 = complex64(X), planes =
-// split(conj(E)); then out = X - XE / 2 (XE = X32 E from the mixed kernel).
-hipError_t launch_ns_prep(const double2* X, const double2* E, float2* X32, uint16_t* planes, int t, hipStream_t s);
-hipError_t launch_ns_update(const double2* X, const float2* XE, double2* out, int t, hipStream_t s);
+// Newton-Schulz correction in split BF16 (mixed form): E = G - I and its
+// defect, X32 = complex64(X) and planes = split(conj(E)) in one pass (E itself
+// not stored); after XE = X32 E on the split-BF16 kernel, out = X - XE / 2
+// and the split of out into the planes in one pass.
+hipError_t launch_ns_prep_fused(const double2* X, const double2* G, const double2* G2, float2* X32, uint16_t* planes,
+                                int t, unsigned long long* defect_bits, hipStream_t s);
+hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* out, uint16_t* planes, int t,
+                                  hipStream_t s);
 // G <- G (+ G2 when not null) - I, and the defect max |G_ij| (atomic max).
 hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
                                       hipStream_t s);
