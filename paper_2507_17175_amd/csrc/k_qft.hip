@@ -87,6 +87,19 @@ __device__ __forceinline__ double2 twiddle(int64_t x, const double2* __restrict_
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// y * w for an element held in the state's precision, in FP64.
+template <typename T, typename R>
+__device__ __forceinline__ T twiddled(R yr, R yi, double2 w) {
+  T o;
+  o.x = R(double(yr) * w.x - double(yi) * w.y);
+  o.y = R(double(yr) * w.y + double(yi) * w.x);
+  return o;
+}
+
 // Largest LDS exchange buffer of a pass (R1 = R2 = 16): 16 x 16 x 16 points.
 constexpr int kQftLds = 4096;
 
@@ -136,37 +149,40 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
       im[a] = v.y;
     }
     dft_regs<R, R1>(re, im);
+    // The twiddles of consecutive m1 are successive powers of one table
+    // value (exp(-2 pi i (j2 2^bits_before) m1 / N) = w1^m1), formed by FP64
+    // products: one table lookup per thread instead of one per output.
     if (R2 == 1) {
       if (ok) {
+        const double2 w1 = twiddle(j2 << bits_before, tw_hi, tw_lo, h);
+        double2 w = make_double2(1.0, 0.0);
 #pragma unroll
         for (int m1 = 0; m1 < R1; ++m1) {
           R yr = re[brev(m1, L1)], yi = im[brev(m1, L1)];
-          int64_t x = (j2 * m1) << bits_before;
           T o;
-          if (x == 0) {
+          if (m1 == 0) {
             o.x = yr;
             o.y = yi;
           } else {
-            double2 w = twiddle(x, tw_hi, tw_lo, h);
-            o.x = R(double(yr) * w.x - double(yi) * w.y);
-            o.y = R(double(yr) * w.y + double(yi) * w.x);
+            w = m1 == 1 ? w1 : cmul(w, w1);
+            o = twiddled<T, R>(yr, yi, w);
           }
           buf0[base + int64_t(m1) * md] = o;
         }
       }
     } else {
+      const double2 w1 = twiddle(int64_t(j1b) << (n - pass_bits), tw_hi, tw_lo, h);
+      double2 w = make_double2(1.0, 0.0);
 #pragma unroll
       for (int m1a = 0; m1a < R1; ++m1a) {
         R yr = re[brev(m1a, L1)], yi = im[brev(m1a, L1)];
-        int64_t x = int64_t(j1b * m1a) << (n - pass_bits);
         T o;
-        if (x == 0) {
+        if (m1a == 0 || j1b == 0) {
           o.x = yr;
           o.y = yi;
         } else {
-          double2 w = twiddle(x, tw_hi, tw_lo, h);
-          o.x = R(double(yr) * w.x - double(yi) * w.y);
-          o.y = R(double(yr) * w.y + double(yi) * w.x);
+          w = m1a == 1 ? w1 : cmul(w, w1);
+          o = twiddled<T, R>(yr, yi, w);
         }
         L[(m1a * R2 + j1b) * E + e] = o;
       }
@@ -189,19 +205,22 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
       im[b] = v.y;
     }
     dft_regs<R, R2>(re, im);
+    // twiddle of m1 = m1a + R1 m1b: exp(-2 pi i j2 m1 2^bits_before / N)
+    // = w0 * ws^m1b with w0 for m1a and ws for the step R1
+    const double2 w0 = twiddle((j2 * m1a) << bits_before, tw_hi, tw_lo, h);
+    const double2 ws = twiddle((j2 * R1) << bits_before, tw_hi, tw_lo, h);
+    double2 w = w0;
 #pragma unroll
     for (int m1b = 0; m1b < R2; ++m1b) {
       const int m1 = m1a + R1 * m1b;
       R yr = re[brev(m1b, L2)], yi = im[brev(m1b, L2)];
-      int64_t x = (j2 * m1) << bits_before;
+      if (m1b > 0) w = cmul(w, ws);
       T o;
-      if (x == 0) {
+      if (j2 == 0 || m1 == 0) {
         o.x = yr;
         o.y = yi;
       } else {
-        double2 w = twiddle(x, tw_hi, tw_lo, h);
-        o.x = R(double(yr) * w.x - double(yi) * w.y);
-        o.y = R(double(yr) * w.y + double(yi) * w.x);
+        o = twiddled<T, R>(yr, yi, w);
       }
       buf0[base + int64_t(m1) * md] = o;
     }
