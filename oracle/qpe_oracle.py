@@ -54,6 +54,7 @@ __all__ = [
     "qpe_probs_krylov",
     "qpe_probs_dense_circuit",
     "fejer",
+    "fejer_at",
     "superposition_probs",
     "estimate_argmax",
     "estimate_weighted",
@@ -219,6 +220,19 @@ def fejer(phi: float, n: int) -> np.ndarray:
     out[exact] = 1.0
     ne = ~exact
     out[ne] = num[ne] / den[ne]
+    return out
+
+
+def fejer_at(phi: float, n: int, m: np.ndarray) -> np.ndarray:
+    """The closed form of fejer(phi, n) at the outcomes m only (for
+    registers too large to tabulate): P(m) = sin^2(pi x) / (N^2 sin^2(pi x /
+    N)), x = N phi - m, and 1 where x is a multiple of N."""
+    N = 1 << n
+    m = np.asarray(m, dtype=np.float64)
+    x = float(N) * float(phi) - m
+    out = np.ones(m.shape, dtype=np.float64)
+    ne = np.mod(x, float(N)) != 0.0
+    out[ne] = np.sin(np.pi * x[ne]) ** 2 / ((float(N) ** 2) * np.sin(np.pi * x[ne] / N) ** 2)
     return out
 
 

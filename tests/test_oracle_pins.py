@@ -78,3 +78,15 @@ def test_circular_estimator_exact_bit_and_wrap():
     P[0] = P[N - 1] = 0.5
     assert abs(O.estimate_circular(P) - (1 - 0.5 / N)) < 1e-14
     assert abs(O.estimate_weighted(P) - (N - 1) / (2 * N)) < 1e-15
+
+
+def test_fejer_at_against_geometric_sum():
+    # the pointwise closed form against |N^-1 sum_j exp(2 pi i j (phi - m/N))|^2
+    for n, phi in [(3, 0.3), (10, 0.7123), (16, 5 / 64), (20, 0.999)]:
+        N = 1 << n
+        m = np.array([0, 1, int(phi * N), int(phi * N) + 1, N - 1, N // 3])
+        j = np.arange(N, dtype=np.float64)
+        direct = np.array([abs(np.exp(2j * np.pi * j * (phi - mm / N)).sum() / N) ** 2 for mm in m])
+        assert np.abs(O.fejer_at(phi, n, m) - direct).max() < 1e-12
+    # and it is the full table's entries
+    assert np.array_equal(O.fejer_at(0.3, 9, np.arange(512)), O.fejer(0.3, 9))
