@@ -421,30 +421,66 @@ struct TableArgs {
 };
 
 // One block per launch: its members in instance order and the prefix sums
-// of their workgroup counts.
-__global__ void k_batch_tables(const InstDesc* __restrict__ desc, int ninst, int32_t* __restrict__ tables,
-                               TableArgs a, int mixed, int bflags) {
-  if (blockIdx.x >= unsigned(a.nlaunch) || threadIdx.x != 0) return;
+// of their workgroup counts. The instances are taken 256 at a time; within
+// a chunk an LDS scan gives each member its slot and its prefix.
+constexpr int kTableThreads = 256;
+
+__global__ void __launch_bounds__(kTableThreads) k_batch_tables(const InstDesc* __restrict__ desc, int ninst,
+                                                                int32_t* __restrict__ tables, TableArgs a,
+                                                                int mixed, int bflags) {
+  if (blockIdx.x >= unsigned(a.nlaunch)) return;  // uniform over the block
   const BatchLaunch L = a.l[blockIdx.x];
   int32_t* tab = tables + L.table_off;
-  int count = 0;
-  for (int i = 0; i < ninst; ++i)
-    if (batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
-                    bflags & kBatchDoubling) > 0)
-      ++count;
-  tab[0] = count;
-  int c = 0;
-  int64_t run = 0;
-  for (int i = 0; i < ninst; ++i) {
-    int64_t tiles = batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
-                                bflags & kBatchDoubling);
-    if (tiles <= 0) continue;
-    tab[1 + c] = i;
-    tab[1 + count + c] = int32_t(run);
-    run += tiles;
-    ++c;
+  const int tid = threadIdx.x;
+  auto tiles_of = [&](int i) -> int64_t {
+    return i < ninst ? batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
+                                   bflags & kBatchDoubling)
+                     : 0;
+  };
+  __shared__ int sc[kTableThreads];
+  __shared__ long long sr[kTableThreads];
+  // number of members (the prefix array follows the member list)
+  int mine = 0;
+  for (int i = tid; i < ninst; i += kTableThreads) mine += tiles_of(i) > 0 ? 1 : 0;
+  sc[tid] = mine;
+  __syncthreads();
+  for (int w = kTableThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sc[tid] += sc[tid + w];
+    __syncthreads();
   }
-  tab[1 + count + count] = int32_t(run);
+  const int count = sc[0];
+  __syncthreads();
+  int carry_c = 0;
+  long long carry_r = 0;
+  for (int base = 0; base < ninst; base += kTableThreads) {
+    const int i = base + tid;
+    const int64_t ti = tiles_of(i);
+    const int f = ti > 0 ? 1 : 0;
+    sc[tid] = f;
+    sr[tid] = ti > 0 ? ti : 0;
+    __syncthreads();
+    // inclusive scans (Hillis-Steele)
+    for (int w = 1; w < kTableThreads; w <<= 1) {
+      const int c = tid >= w ? sc[tid - w] : 0;
+      const long long r = tid >= w ? sr[tid - w] : 0;
+      __syncthreads();
+      sc[tid] += c;
+      sr[tid] += r;
+      __syncthreads();
+    }
+    if (f) {
+      const int slot = carry_c + sc[tid] - 1;
+      tab[1 + slot] = i;
+      tab[1 + count + slot] = int32_t(carry_r + sr[tid] - ti);
+    }
+    carry_c += sc[kTableThreads - 1];
+    carry_r += sr[kTableThreads - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    tab[0] = count;
+    tab[1 + count + count] = int32_t(carry_r);
+  }
 }
 
 // --------------------------------------------------------- batched kernels
@@ -663,7 +699,8 @@ hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables,
   TableArgs a{};
   a.nlaunch = nlaunch;
   for (int i = 0; i < nlaunch; ++i) a.l[i] = launches[i];
-  hipLaunchKernelGGL(k_batch_tables, dim3(nlaunch), dim3(64), 0, s, desc, ninst, tables, a, mixed ? 1 : 0, bflags);
+  hipLaunchKernelGGL(k_batch_tables, dim3(nlaunch), dim3(kTableThreads), 0, s, desc, ninst, tables, a, mixed ? 1 : 0,
+                     bflags);
   return hipGetLastError();
 }
 
