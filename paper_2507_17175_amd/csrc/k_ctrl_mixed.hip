@@ -291,10 +291,13 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       for (int c = 0; c < 6; ++c) {
         if (c >= C0) mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
         __builtin_amdgcn_sched_barrier(0);
-        if (c < 4) split_part(c);
-        if (c == 3) write_a(nb);
-        if (c == 4) write_b(nb);
-        if (c == 5) load_global(ns);
+        if (c == 0) write_b(nb);
+        if (c < 2) {
+          split_part(2 * c);
+          split_part(2 * c + 1);
+        }
+        if (c == 1) write_a(nb);
+        if (c == 2) load_global(ns);
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
