@@ -18,15 +18,22 @@
 // planes (hi/mid/lo x re/im), blocked by 16 columns so that the K slab of a
 // column tile is one contiguous run.
 //
-// Two kernels:
-//  * k_ctrl_bf16x6_db (default): 8 wave64s (two per SIMD, so one wave's LDS
-//    waits are covered by the other's matrix-core work), K slab of 16
-//    complex, double-buffered LDS: the split-and-store of slab s+1 and the
-//    global loads of slab s+2 overlap the MFMAs of slab s, one barrier per
-//    slab. LDS rows are padded to 48 bytes: the 16-byte fragment reads of 16
-//    consecutive rows then cover all 64 banks once.
-//  * k_ctrl_bf16x6 (variant 1): 4 wave64s, K slab of 32 complex, single
-//    LDS buffer with register prefetch.
+// Kernels:
+//  * k_ctrl_bf16x6_db (variant 2; the default below eight tiles per CU): 8
+//    wave64s (two per SIMD, so one wave's LDS waits are covered by the
+//    other's matrix-core work), K slab of 16 complex, double-buffered LDS:
+//    the split-and-store of slab s+1 and the global loads of slab s+2 are
+//    interleaved with the MFMAs of slab s, one barrier per slab. LDS rows are
+//    padded to 48 bytes: the 16-byte fragment reads of 16 consecutive rows
+//    then cover all 64 banks once.
+//  * k_ctrl_bf16x6_pp (variant 6; the default from eight tiles per CU): the
+//    same tile and buffers, with the two waves of each SIMD one phase apart:
+//    one runs a slab's MFMAs while the other does its LDS and memory work.
+//  * k_ctrl_bf16x6 (variant 1, and the small-launch default): 4 wave64s, K
+//    slab of 32 complex, single LDS buffer with register prefetch.
+//  * variants 3-5: the double-buffered kernel with the compiler's own issue
+//    order, a triple-buffered swizzled-LDS kernel, and one that takes the
+//    operator fragments from L2 straight into registers.
 #include <type_traits>
 
 #include "qpe_internal.hpp"
@@ -318,6 +325,170 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
   ctrl_db_tile<BM, BN, WM, WN, IL, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+// ----------------------------------------------------------------- variant 6
+// Ping-pong issue: the eight waves form two groups of four (waves 0-3 and
+// 4-7; each SIMD holds one wave of each) that run the same slab loop one
+// phase apart. A slab has a memory phase (fragment reads of slab s, split
+// and LDS stores of slab s+1, global loads of slab s+2) and a matrix phase
+// (the 48 MFMAs of slab s), and every phase ends at a workgroup barrier, so
+// on each SIMD one wave feeds the matrix core while the other does its
+// memory work. Buffer hazards: slab s+1 is stored into buffer (s+1)&1 by
+// group 0 in phase 2s and by group 1 in phase 2s+1; that buffer was last
+// read (slab s-1) in phases 2s-2 and 2s-1, and is read again (slab s+1) in
+// phases 2s+2 and 2s+3, each on the other side of a barrier.
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ctrl_pp_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                             const uint16_t* __restrict__ planes, int n, int t, int k,
+                                             uint64_t pmask, int tile_m, int tile_n) {
+  constexpr int NT = 512;
+  static_assert(WM * WN == 8, "8 waves");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KS = 16;
+  constexpr int ROW = 24;
+  constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
+  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int CA = BM * KS / 4 / NT;
+  constexpr int NB = 12 * BN;
+  constexpr int CB = (NB + NT - 1) / NT;
+  static_assert(CA >= 1 && CA * NT * 4 == BM * KS, "tile/thread mismatch");
+
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = wave >> 2;
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+
+  const float2* src_row[CA];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int c = tid + q * NT;
+    int gi = min(i0 + c / 4, M - 1);
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+  }
+
+  float4 ra[CA][2];
+  u32x4 rb[CB];
+  auto load_global = [&](int s) {
+    const int k0 = s * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[q][0] = p[0];
+      ra[q][1] = p[1];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      rb[q] = *reinterpret_cast<const u32x4*>(planes + pl * dd + (int64_t(s) * d + j0 + (w >> 1)) * kPlaneBlock +
+                                              8 * (w & 1));
+    }
+  };
+  auto store_lds = [&](int b) {
+    uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      bf16x4 pc[6];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 w = ra[q][u >> 1];
+        __bf16 h, m, l;
+        split3((u & 1) ? w.z : w.x, h, m, l);
+        pc[0][u] = h;
+        pc[2][u] = m;
+        pc[4][u] = l;
+        split3((u & 1) ? w.w : w.y, h, m, l);
+        pc[1][u] = h;
+        pc[3][u] = m;
+        pc[5][u] = l;
+      }
+      int c = tid + q * NT;
+      int r = c / 4, kq = c & 3;
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[pl];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = tid + q * NT;
+      if (NB % NT != 0 && idx >= NB) break;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      *reinterpret_cast<u32x4*>(base + 6 * A_PLANE + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[x][y][v] = 0.f;
+        acc_im[x][y][v] = 0.f;
+      }
+
+  const int nk = d / KS;
+  const int lr = lane & 31, ko = (lane >> 5) * 8;
+  load_global(0);
+  store_lds(0);
+  if (nk > 1) load_global(1);
+  __syncthreads();
+  if (grp == 1) __syncthreads();
+
+  for (int s = 0; s < nk; ++s) {
+    // memory phase
+    const uint16_t* base = lds + (s & 1) * BUF;
+    bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bv[y][pl] =
+            *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+    // As in the double-buffered kernel, the store of slab s+1 and the loads
+    // of slab s+2 are unconditional (the last slabs rewrite the idle buffer
+    // and reload slab nk-1).
+    store_lds((s + 1) & 1);
+    load_global(min(s + 2, nk - 1));
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    // matrix phase
+    mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (grp == 0) __syncthreads();
+
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_pp_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -884,13 +1055,20 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 5; }
+int ctrl_mixed_variants() { return 6; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant) {
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (variant == 6) {
+    // ping-pong wave groups
+    if (t >= 7) return launch<512>(k_ctrl_bf16x6_pp<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6) return launch<512>(k_ctrl_bf16x6_pp<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }
@@ -922,6 +1100,10 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
   const int64_t big_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
   if (t >= 6 && big_tiles < 256)
     return launch<256>(k_ctrl_bf16x6<64, 64, 2, 2>, 64, 64, buf0, buf1, planes, n, t, k, pmask, s);
+  // At eight or more tiles per CU the ping-pong kernel is a few per cent
+  // faster; below that (the middle prefix-doubling steps) the interleaved one.
+  if (variant == 0 && t >= 7 && big_tiles >= 2048)
+    return launch<512>(k_ctrl_bf16x6_pp<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t >= 7) return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
