@@ -373,7 +373,7 @@ def main():
     avg_s = (g_ms / g_cnt) / 1e3 if g_cnt else float("nan")
     achieved = flops_per_launch / avg_s / 1e12
     roofline = {
-        "kernel": ("k_ctrl_bf16x6_pp<128,128> (controlled product, split-BF16 x6 on MFMA)"
+        "kernel": ("k_ctrl_bf16x6_pp2<128,128> (controlled product, split-BF16 x6 on MFMA)"
                    if not tuned else "k_ctrl_bf16x6 (variant picked by the autotuner)") if t >= 5 else "k_ctrl_small",
         "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_BF16_TFLOPS, 4),

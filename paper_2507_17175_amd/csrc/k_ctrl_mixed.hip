@@ -26,9 +26,12 @@
 //    interleaved with the MFMAs of slab s, one barrier per slab. LDS rows are
 //    padded to 48 bytes: the 16-byte fragment reads of 16 consecutive rows
 //    then cover all 64 banks once.
-//  * k_ctrl_bf16x6_pp (variant 6; the default from eight tiles per CU): the
-//    same tile and buffers, with the two waves of each SIMD one phase apart:
-//    one runs a slab's MFMAs while the other does its LDS and memory work.
+//  * k_ctrl_bf16x6_pp (variant 6): the same tile and buffers, with the two
+//    waves of each SIMD one phase apart: one runs a slab's MFMAs while the
+//    other does its LDS and memory work.
+//  * k_ctrl_bf16x6_pp2 (variant 7; the default from eight tiles per CU): as
+//    variant 6, but each wave group splits and stores its own state rows
+//    during its matrix phase, one MFMA at a time between the vector work.
 //  * k_ctrl_bf16x6 (variant 1, and the small-launch default): 4 wave64s, K
 //    slab of 32 complex, single LDS buffer with register prefetch.
 //  * variants 3-5: the double-buffered kernel with the compiler's own issue
@@ -489,6 +492,202 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp(float2* __restrict__ buf
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
   ctrl_pp_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+// ----------------------------------------------------------------- variant 7
+// Ping-pong with the state half of the tile private to each wave group:
+// waves 0-3 use state rows 0-63 and waves 4-7 rows 64-127, so each group
+// splits and stores its own rows of slab s+1 during its matrix phase of slab
+// s (interleaved with its MFMAs), and the memory phase keeps only the
+// fragment reads and the shared operator half. Hazards (group g's memory
+// phase of slab s is phase 2s+g, its matrix phase 2s+1+g): its rows of
+// buffer (s+1)&1 are written in phase 2s+1+g, read in 2s+2+g and were last
+// read in 2s-2+g; the operator half is handled as in variant 6.
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                              const uint16_t* __restrict__ planes, int n, int t, int k,
+                                              uint64_t pmask, int tile_m, int tile_n) {
+  constexpr int NT = 512, NG = 256;  // threads per workgroup, per group
+  static_assert(WM == 2 && WN == 4, "a group is one row half of the tile");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KS = 16;
+  constexpr int ROW = 24;
+  constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
+  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int CA = TM * KS / 4 / NG;  // 4-complex chunks of the group's rows per thread
+  constexpr int NB = 12 * BN / 2;       // 16-byte operator chunks per group
+  constexpr int CB = (NB + NG - 1) / NG;
+  static_assert(CA >= 1 && CA * NG * 4 == TM * KS, "tile/thread mismatch");
+  static_assert(NB % NG == 0, "operator chunks per group");
+
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = wave >> 2, tg = tid & (NG - 1);
+  const int i0 = tile_m * BM, j0 = tile_n * BN;
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;  // wi0 = grp * TM
+
+  const float2* src_row[CA];
+#pragma unroll
+  for (int q = 0; q < CA; ++q) {
+    int c = tg + q * NG;
+    int gi = min(i0 + wi0 + c / 4, M - 1);
+    int64_t j = step_row(gi, k, pmask);
+    src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+  }
+
+  float4 ra[CA][2];
+  u32x4 rb[CB];
+  auto load_a = [&](int s) {
+    const int k0 = s * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[q][0] = p[0];
+      ra[q][1] = p[1];
+    }
+  };
+  auto load_b = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = grp * NB + tg + q * NG;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      rb[q] = *reinterpret_cast<const u32x4*>(planes + pl * dd + (int64_t(s) * d + j0 + (w >> 1)) * kPlaneBlock +
+                                              8 * (w & 1));
+    }
+  };
+  bf16x4 pc[CA][6];
+  auto split_part = [&](int u) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4 w = ra[q][u >> 1];
+      __bf16 h, m, l;
+      split3((u & 1) ? w.z : w.x, h, m, l);
+      pc[q][0][u] = h;
+      pc[q][2][u] = m;
+      pc[q][4][u] = l;
+      split3((u & 1) ? w.w : w.y, h, m, l);
+      pc[q][1][u] = h;
+      pc[q][3][u] = m;
+      pc[q][5][u] = l;
+    }
+  };
+  auto write_a = [&](int b) {
+    uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tg + q * NG;
+      int r = wi0 + c / 4, kq = c & 3;
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
+    }
+  };
+  auto write_b = [&](int b) {
+    uint16_t* base = lds + b * BUF + 6 * A_PLANE;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      int idx = grp * NB + tg + q * NG;
+      int pl = idx / (BN * 2), w = idx % (BN * 2);
+      *reinterpret_cast<u32x4*>(base + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc_re[x][y][v] = 0.f;
+        acc_im[x][y][v] = 0.f;
+      }
+
+  const int nk = d / KS;
+  const int lr = lane & 31, ko = (lane >> 5) * 8;
+  load_a(0);
+  load_b(0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_part(u);
+  write_a(0);
+  write_b(0);
+  if (nk > 1) {
+    load_a(1);
+    load_b(1);
+  }
+  __syncthreads();
+  if (grp == 1) __syncthreads();
+
+  for (int s = 0; s < nk; ++s) {
+    const int nb = (s + 1) & 1, ns = min(s + 2, nk - 1);
+    // memory phase: fragments of slab s, the group's operator chunks of
+    // slab s+1 (unconditional, as in the other kernels), loads of slab s+2
+    const uint16_t* base = lds + (s & 1) * BUF;
+    bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bv[y][pl] =
+            *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+    write_b(nb);
+    load_b(ns);
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pc2 = 0; pc2 < 3; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    // matrix phase, with the split and store of the group's rows of slab s+1
+    // spread thinly between the MFMAs (one MFMA, then up to three VALU ops)
+    mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_part(u);
+    write_a(nb);
+    load_a(ns);
+#pragma unroll
+    for (int i = 0; i < 26; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 17, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (grp == 0) __syncthreads();
+
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp2(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                          const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                          uint64_t pmask) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_pp2_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -1055,13 +1254,20 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 6; }
+int ctrl_mixed_variants() { return 7; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant) {
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
+    return hipErrorInvalidValue;
+  }
+  if (variant == 7) {
+    // ping-pong with group-private state rows
+    if (t >= 7) return launch<512>(k_ctrl_bf16x6_pp2<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    if (t == 6) return launch<512>(k_ctrl_bf16x6_pp<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
     return hipErrorInvalidValue;
   }
@@ -1100,10 +1306,11 @@ hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes,
   const int64_t big_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
   if (t >= 6 && big_tiles < 256)
     return launch<256>(k_ctrl_bf16x6<64, 64, 2, 2>, 64, 64, buf0, buf1, planes, n, t, k, pmask, s);
-  // At eight or more tiles per CU the ping-pong kernel is a few per cent
-  // faster; below that (the middle prefix-doubling steps) the interleaved one.
+  // At eight or more tiles per CU the ping-pong kernel with group-private
+  // state rows is a few per cent faster; below that (the middle
+  // prefix-doubling steps) the interleaved one.
   if (variant == 0 && t >= 7 && big_tiles >= 2048)
-    return launch<512>(k_ctrl_bf16x6_pp<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
+    return launch<512>(k_ctrl_bf16x6_pp2<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t >= 7) return launch<512>(k_ctrl_bf16x6_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 6) return launch<512>(k_ctrl_bf16x6_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
   if (t == 5) return launch<256>(k_ctrl_bf16x6<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s);
