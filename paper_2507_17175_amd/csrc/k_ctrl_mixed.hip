@@ -1198,7 +1198,9 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 }
 
 // Grouped controlled step k over the instances of a launch table; the tile
-// shape follows the operator size class of the launch (d = 32, 64, >= 128).
+// shape follows the operator size class of the launch (d = 32, 64, >= 128;
+// the last with the ping-pong schedule, which gives the same bits as the
+// in-step one).
 // The BK_NS_* kinds run the Newton-Schulz correction X E of power step
 // `step` instead: X (complex64, in tbuf) rows [0, d) times the split planes of
 // E, written to gbuf, through the prefix-doubling mapping of a t+1 qubit
@@ -1239,8 +1241,10 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
     ctrl_v1_tile<128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else if constexpr (BN == 64)
     ctrl_db_tile<128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
-  else
+  else if constexpr (NS)
     ctrl_db_tile<128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+  else
+    ctrl_pp2_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
 }
 
 template <int NT, typename K>
