@@ -560,9 +560,11 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
     case BK_PROB: {
       const int G = d < 64 ? d : 64;
       const int rows_per_wave = 64 / G;
-      int64_t base = (local * 4 + (threadIdx.x >> 6)) * rows_per_wave;
-      prob_rows<T>(reinterpret_cast<const T*>(D.ws + L.state0), D.prob, n, t, make_dft_plan(n), ldexp(1.0, -n),
-                   base);
+      const DftPlan plan = make_dft_plan(n);
+      for (int r = 0; r < kProbRounds; ++r) {
+        const int64_t base = ((local * kProbRounds + r) * 4 + (threadIdx.x >> 6)) * rows_per_wave;
+        prob_rows<T>(reinterpret_cast<const T*>(D.ws + L.state0), D.prob, n, t, plan, ldexp(1.0, -n), base);
+      }
       break;
     }
     case BK_REPORT:

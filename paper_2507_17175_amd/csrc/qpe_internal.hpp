@@ -176,6 +176,7 @@ constexpr int kHTile = 4096;     // complex amplitudes per H-layer tile
 constexpr int kSplitTile = 4096; // operator elements per split tile
 constexpr int kSubiTile = 16384; // operator elements per identity-subtraction tile
 constexpr int kBatchGemmTile = 32;
+constexpr int kProbRounds = 8;   // row groups per readout workgroup
 
 struct InstDesc {
   int32_t n, t;
@@ -250,7 +251,7 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     }
     case BK_PROB: {
       int64_t G = d < 64 ? d : 64;
-      return cdiv(N, 4 * (64 / G));
+      return cdiv(N, 4 * (64 / G) * kProbRounds);
     }
     case BK_REPORT:
       return 1;
@@ -259,17 +260,25 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
 }
 
 // Instance and local tile of workgroup `tile` in a launch table.
+// The first tile of each member, pre[], rises strictly from pre[0] = 0, so
+// the member is the last entry <= tile. Each round the 64 lanes of the wave
+// sample the remaining range at 64 evenly spaced entries (one load each) and
+// a ballot picks the segment: two dependent rounds up to 4096 members,
+// instead of a binary search's log2(count). Every lane of a full wave must
+// call it (all grouped kernels do, first thing, with blocks of whole waves).
 __device__ inline int find_member(const int32_t* __restrict__ tab, int64_t tile, int64_t* local) {
   const int count = tab[0];
   const int32_t* mem = tab + 1;
   const int32_t* pre = tab + 1 + count;
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= tile)
-      lo = mid;
-    else
-      hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, len = count;  // invariant: pre[lo] <= tile, the answer is in [lo, lo + len)
+  while (len > 1) {
+    const int step = (len + 63) >> 6;
+    const bool le = lane * step < len && pre[lo + lane * step] <= tile;
+    const unsigned long long m = __ballot(le);  // bit 0 is set: pre[lo] <= tile
+    const int last = 63 - __clzll(m);
+    lo += last * step;
+    len = min(step, len - last * step);
   }
   *local = tile - pre[lo];
   return mem[lo];
