@@ -306,11 +306,15 @@ def scaling_study_main(a) -> int:
 
 
 def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
+    """Times `steps` circuits with HIP events around the controlled-product
+    launches only (the roofline figure); the per-stage breakdown comes from
+    two more circuits with every stage timed, after the timed region."""
     run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])], form=form, flags=flags)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
     run.ctx.enable_timing(80 * steps + 64)
+    run.ctx.set_timing_mask(["ctrl_gemm"])
     run.ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -319,6 +323,12 @@ def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timing = run.ctx.read_timing()
+    run.ctx.set_timing_mask(None)
+    run.ctx.reset_timing()
+    for _ in range(2):
+        run()
+    stages = run.ctx.read_timing()
+    timing.update({k: (v[0] * steps // 2, v[1] * steps / 2) for k, v in stages.items() if k != "ctrl_gemm"})
     rep = run.reports()[0]
     P = run.probs[0].cpu().numpy()
     return (t1 - t0), timing, rep, P

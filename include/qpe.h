@@ -253,6 +253,11 @@ enum {
   QPE_TIMER_COUNT = 6
 };
 qpe_status qpe_ctx_enable_timing(qpe_ctx *ctx, int max_pairs);
+/* Timer classes that record events: bit c set = class c timed (all by
+ * default); launches of the other classes are not bracketed, so their
+ * events cost nothing. QPE_ERR_ARG for NULL ctx or bits beyond
+ * QPE_TIMER_COUNT. */
+qpe_status qpe_ctx_set_timing_mask(qpe_ctx *ctx, unsigned mask);
 qpe_status qpe_ctx_reset_timing(qpe_ctx *ctx);
 qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *total_ms);
 

@@ -36,6 +36,7 @@ struct qpe_ctx {
   std::vector<qpe_timer_pair> timers;
   size_t timers_used = 0;
   bool timing = false;
+  unsigned timer_mask = (1u << QPE_TIMER_COUNT) - 1;  // timer classes that record events
   // kernel variant per class (0 = default)
   int variant[QPE_KERNEL_COUNT][QPE_MAX_N_MAT + 1] = {};
 };
@@ -194,7 +195,7 @@ struct TimerScope {
   qpe_ctx* ctx;
   long idx = -1;
   TimerScope(qpe_ctx* c, int which) : ctx(c) {
-    if (which >= 0 && c->timing && c->timers_used < c->timers.size()) {
+    if (which >= 0 && c->timing && ((c->timer_mask >> which) & 1u) && c->timers_used < c->timers.size()) {
       idx = long(c->timers_used++);
       c->timers[idx].which = which;
       (void)hipEventRecord(c->timers[idx].start, c->stream);
@@ -616,6 +617,12 @@ QPE_API qpe_status qpe_ctx_enable_timing(qpe_ctx* ctx, int max_pairs) {
     ctx->timers.push_back(p);
   }
   ctx->timing = true;
+  return QPE_OK;
+}
+
+QPE_API qpe_status qpe_ctx_set_timing_mask(qpe_ctx* ctx, unsigned mask) {
+  if (!ctx || (mask >> QPE_TIMER_COUNT) != 0u) return QPE_ERR_ARG;
+  ctx->timer_mask = mask;
   return QPE_OK;
 }
 

@@ -38,7 +38,7 @@ EXPORTS = (
     "qpe_powers_workspace_size", "qpe_powers", "qpe_controlled_step_workspace_size",
     "qpe_controlled_step", "qpe_iqft_workspace_size", "qpe_iqft_probs", "qpe_zgemm",
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
-    "qpe_ctx_enable_timing", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
+    "qpe_ctx_enable_timing", "qpe_ctx_set_timing_mask", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
     "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
     "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune",
 )
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                vp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), vp, i32, vp, i32]),
             "qpe_check_run": (st, [ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, vp, sz, vp]),
             "qpe_ctx_enable_timing": (st, [vp, i32]),
+            "qpe_ctx_set_timing_mask": (st, [vp, ctypes.c_uint]),
             "qpe_ctx_reset_timing": (st, [vp]),
             "qpe_kernel_variants": (st, [i32, ctypes.POINTER(i32)]),
             "qpe_ctx_set_variant": (st, [vp, i32, i32, i32]),
@@ -210,6 +211,12 @@ class Context:
 
     def enable_timing(self, max_pairs: int = 4096) -> None:
         _check(load_library().qpe_ctx_enable_timing(self.handle, int(max_pairs)), "qpe_ctx_enable_timing",
+               self.handle)
+
+    def set_timing_mask(self, classes=None) -> None:
+        """Time only the named classes (None: all of them)."""
+        mask = (1 << len(TIMERS)) - 1 if classes is None else sum(1 << TIMERS[c] for c in classes)
+        _check(load_library().qpe_ctx_set_timing_mask(self.handle, ctypes.c_uint(mask)), "qpe_ctx_set_timing_mask",
                self.handle)
 
     def reset_timing(self) -> None:

@@ -110,6 +110,7 @@ def test_null_context(L):
     al = (ctypes.c_double * 2)(1.0, 0.0)
     assert L.qpe_zgemm(None, b"N", b"N", 4, 4, 4, al, 0x1000, 4, 0x1000, 4, al, 0x1000, 4, 0x1000, 4) == 1
     assert L.qpe_powers(None, 2, 0x1000, 3, 0, 0x1000, 0x100000, 1 << 20, None) == 1
+    assert L.qpe_ctx_set_timing_mask(None, 1) == 1
     assert L.qpe_ctx_destroy(None) == 0
     assert L.qpe_last_error(None) == b""
 
