@@ -341,7 +341,7 @@ def main():
     if a.warmup is None:
         a.warmup = 0 if a.config == "c5" else 3
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {a.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         return 2
     if a.copy_probe_mib:

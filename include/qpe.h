@@ -50,7 +50,7 @@ typedef enum qpe_status {
   QPE_ERR_OOM = 5,         /* host allocation for the context failed       */
   QPE_ERR_NO_DEVICE = 6,   /* no HIP device, or the device index is invalid*/
   QPE_ERR_HIP = 7,         /* a HIP runtime call or a kernel launch failed */
-  QPE_ERR_UNSUPPORTED = 8  /* valid request this build does not implement  */
+  QPE_ERR_UNSUPPORTED = 8  /* valid request the library does not implement */
 } qpe_status;
 
 /* Arithmetic form of the statevector path.

@@ -450,7 +450,7 @@ const char* const kStatusText[] = {
     "QPE_ERR_OOM: host allocation failed",
     "QPE_ERR_NO_DEVICE: no usable HIP device",
     "QPE_ERR_HIP: a HIP call or kernel launch failed",
-    "QPE_ERR_UNSUPPORTED: not implemented in this build",
+    "QPE_ERR_UNSUPPORTED: not implemented by this library",
 };
 
 }  // namespace
