@@ -389,8 +389,11 @@ def main():
         "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
         "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
         "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt,
-        "traffic": traffic_for_current_kernel() if (a.config == "c2" and t >= 5 and not tuned) else None,
     }
+    # traffic: HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE), or null
+    tr = traffic_for_current_kernel() if (a.config == "c2" and t >= 5 and not tuned) else None
+    roofline["traffic"] = tr["bytes_per_launch"] if tr else None
+    roofline["traffic_detail"] = tr
     breakdown = {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing.items()}
 
     out = {
