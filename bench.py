@@ -305,6 +305,25 @@ def scaling_study_main(a) -> int:
     return 0
 
 
+def batch_of_copies(qpe, torch, prob, copies, steps, P_single):
+    """`copies` copies of one instance as one batched run, captured in a HIP
+    graph and replayed `steps` times; every copy's P must equal the single
+    run's bit for bit."""
+    run = qpe.Runner([(prob["U"], prob["psi"], prob["n"])] * copies, form="mixed")
+    run()
+    torch.cuda.synchronize()
+    graph = qpe.CapturedRun(run)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    same = all(np.array_equal(P.cpu().numpy(), P_single) for P in run.probs[:: max(1, copies // 64)])
+    return {"instances": copies, "circuits_per_s": round(copies * steps / el, 1),
+            "ms_per_batch": round(1e3 * el / steps, 3), "copies_equal_single_run": bool(same)}
+
+
 def time_form(qpe, torch, prob, form, steps, warmup, flags=0):
     """Times `steps` circuits with HIP events around the controlled-product
     launches only (the roofline figure); the per-stage breakdown comes from
@@ -433,6 +452,11 @@ def main():
     }
 
     out["end_to_end_mixed"] = end_to_end(qpe, torch, p, "mixed")
+
+    if a.config == "c1":
+        # A 2^10-amplitude circuit is launch-bound on its own: also time it as
+        # a batch of identical instances (one grouped run, replayed graph).
+        out["batch_of_copies"] = batch_of_copies(qpe, torch, prob, 4096, a.steps, P_mixed)
 
     if not a.no_fp64:
         fsteps = a.fp64_steps or max(3, a.steps // 2)
