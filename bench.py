@@ -74,6 +74,11 @@ def bench_batch(a, qpe, torch, config_problems):
     probs = config_problems(a.config)
     items = [(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas) for p in probs]
     run = qpe.Runner(items, form="mixed")
+    tuned = None
+    if getattr(a, "autotune", False) and not getattr(a, "no_autotune", False):
+        # the batch autotuner picks the grouped kernels' variants (a few
+        # batched runs per variant, before and outside the timed region)
+        tuned = run.autotune(reps=2)
     for _ in range(a.warmup):
         run()
     torch.cuda.synchronize()
@@ -106,6 +111,7 @@ def bench_batch(a, qpe, torch, config_problems):
         "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
         "data": "synthetic (seeded Haar unitaries, eigenvector inputs)",
         "config": {"workload": CONFIGS[a.config], "instances": count, "form": "mixed", "graph": True},
+        "autotune": tuned,
         "eager_ms_per_step": round(1e3 * el / a.steps, 3),
         "ctrl_gemm": {"algorithmic_flops_per_step": flops, "ms_per_step": round(g_ms / a.steps, 3),
                       "achieved_tflops": round(flops / (g_ms / a.steps / 1e3) / 1e12, 2),

@@ -270,7 +270,13 @@ enum {
   QPE_KERNEL_CTRL_MIXED = 0, /* split-BF16 controlled GEMM (d >= 32)  */
   QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain          */
   QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
-  QPE_KERNEL_COUNT = 3
+  /* Batched runs (count > 1). One setting per context: n_mat is checked
+   * but the choice applies to every instance size. */
+  QPE_KERNEL_BATCH_CTRL = 3, /* grouped split-BF16 controlled step, d >= 128:
+                                1 in-step schedule, 2 ping-pong (default) */
+  QPE_KERNEL_BATCH_GEMM = 4, /* grouped FP64 power-chain products: 1 32x32
+                                tiles (default), 2 64x64 tiles for d >= 64 */
+  QPE_KERNEL_COUNT = 5
 };
 qpe_status qpe_kernel_variants(int kernel_class, int *count);
 /* n_mat selects the operator size the choice applies to (0..QPE_MAX_N_MAT),
@@ -297,6 +303,17 @@ qpe_status qpe_ctx_get_variant(const qpe_ctx *ctx, int kernel_class, int n_mat, 
 qpe_status qpe_autotune(qpe_ctx *ctx, const qpe_problem *problem, int form, unsigned flags,
                         void *workspace, size_t workspace_bytes, int reps, int *chosen,
                         double *class_ms);
+
+/* The same for a batched run (the grouped kernels of `count` >= 2 problems):
+ * each batched class this batch uses (QPE_KERNEL_BATCH_GEMM when any
+ * instance has n_meas >= 2, QPE_KERNEL_BATCH_CTRL in the mixed form when
+ * any instance has n_mat >= 7) is timed over whole batched runs, every
+ * variant in turn, and the fastest is kept. Arguments, outputs and errors
+ * as qpe_autotune, with the problems, count and workspace of qpe_run;
+ * every problem's prob vector is overwritten. */
+qpe_status qpe_autotune_batch(qpe_ctx *ctx, const qpe_problem *problems, int count, int form,
+                              unsigned flags, void *workspace, size_t workspace_bytes, int reps,
+                              int *chosen, double *class_ms);
 
 /* ---- misc ---- */
 

@@ -1199,13 +1199,13 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 
 // Grouped controlled step k over the instances of a launch table; the tile
 // shape follows the operator size class of the launch (d = 32, 64, >= 128;
-// the last with the ping-pong schedule, which gives the same bits as the
-// in-step one).
+// the last with the ping-pong schedule, or the in-step one when INSTEP:
+// both give the same bits).
 // The BK_NS_* kinds run the Newton-Schulz correction X E of power step
 // `step` instead: X (complex64, in tbuf) rows [0, d) times the split planes of
 // E, written to gbuf, through the prefix-doubling mapping of a t+1 qubit
 // register.
-template <int KIND>
+template <int KIND, bool INSTEP = false>
 __global__ void __launch_bounds__(KIND == BK_CTRL_M32 || KIND == BK_NS_M32 ? 256 : 512)
 kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags,
               int64_t tile0) {
@@ -1241,7 +1241,7 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
     ctrl_v1_tile<128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else if constexpr (BN == 64)
     ctrl_db_tile<128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
-  else if constexpr (NS)
+  else if constexpr (NS || INSTEP)
     ctrl_db_tile<128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
   else
     ctrl_pp2_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
@@ -1350,6 +1350,10 @@ hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, con
         hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M64>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
       });
     case BK_CTRL_M128:
+      if (bflags & kBatchCtrlInStep)
+        return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+          hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M128, true>), dim3(g), dim3(512), 0, s, step, desc, table, p, b);
+        });
       return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
         hipLaunchKernelGGL(kb_ctrl_mixed<BK_CTRL_M128>, dim3(g), dim3(512), 0, s, step, desc, table, p, b);
       });

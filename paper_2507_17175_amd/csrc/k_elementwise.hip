@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(kTableThreads) k_batch_tables(const InstDesc* 
   const int tid = threadIdx.x;
   auto tiles_of = [&](int i) -> int64_t {
     return i < ninst ? batch_tiles(L.kind, L.step, desc[i].n, desc[i].t, mixed != 0, bflags & kBatchPolar,
-                                   bflags & kBatchDoubling)
+                                   bflags & kBatchDoubling, bflags)
                      : 0;
   };
   __shared__ int sc[kTableThreads];

@@ -241,10 +241,14 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
             o.x += a.beta.x * c.x - a.beta.y * c.y;
             o.y += a.beta.x * c.y + a.beta.y * c.x;
           }
+          // Hermitian product: only tiles on or above the diagonal run; an
+          // element below the diagonal is always the conjugate of the one
+          // above it (never computed directly, also inside a diagonal tile),
+          // so the result does not depend on the tile size (the Gauss form
+          // rounds C[i][j] and conj(C[j][i]) differently).
+          if (a.herm && gi > gj) continue;
           a.C[int64_t(gi) * a.ldc + gj] = o;
-          // Hermitian product: only tiles on or above the diagonal run, and
-          // the ones above it also fill their mirror image.
-          if (a.herm && tile_n > tile_m) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
+          if (a.herm && gi < gj) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
         }
       }
 }
@@ -292,11 +296,12 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
 // Power-chain products of step k for every instance that takes part, with
 // 32 x 32 tiles: BK_SQ  X_k = V_{k-1} V_{k-1};  BK_GRAM  G = X^H X;
 // BK_CORR  V_k = X - X (G - I) / 2.
-template <int KIND>
+// G64: instances with d >= 64 take 64 x 64 tiles (4 waves, 32 x 32 each),
+// the others 32 x 32; the tile shape does not change the order of any sum.
+template <int KIND, bool G64>
 __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __restrict__ desc,
                                                 const int32_t* __restrict__ table, int mixed, int bflags,
                                                 int64_t tile0) {
-  constexpr int T = kBatchGemmTile;
   constexpr int OPA = KIND == BK_GRAM ? OP_C : OP_N;
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
@@ -304,6 +309,8 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
   const bool pol = (bflags & kBatchPolar) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed != 0, pol);
   const int d = 1 << D.t;
+  const bool big = G64 && D.t >= 6;
+  const int T = big ? 64 : kBatchGemmTile;
   const int tiles_n = int((d + T - 1) / T);
   double2* vbuf = reinterpret_cast<double2*>(D.ws + L.vbuf);
   double2* tbuf = reinterpret_cast<double2*>(D.ws + L.tbuf);
@@ -345,9 +352,22 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
       a.K /= 2;
     }
     const int2 tile = upper_tile(w, tiles_n);
-    zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, tile.x, tile.y);
+    if constexpr (G64) {
+      if (big) {
+        zgemm_tile<OPA, OP_N, false, 64, 64, 2, 2>(a, g, tile.x, tile.y);
+        return;
+      }
+    }
+    zgemm_tile<OPA, OP_N, false, kBatchGemmTile, kBatchGemmTile, 2, 2>(a, g, tile.x, tile.y);
   } else {
-    zgemm_tile<OPA, OP_N, false, T, T, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+    if constexpr (G64) {
+      if (big) {
+        zgemm_tile<OPA, OP_N, false, 64, 64, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
+        return;
+      }
+    }
+    zgemm_tile<OPA, OP_N, false, kBatchGemmTile, kBatchGemmTile, 2, 2>(a, g, int(local / tiles_n),
+                                                                       int(local % tiles_n));
   }
 }
 
@@ -462,19 +482,19 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
 hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                               bool mixed, int bflags, hipStream_t s) {
   const int m = mixed ? 1 : 0, p = bflags;
+  const bool g64 = (bflags & kBatchGemm64) != 0;
+  auto go_kind = [&](auto kernel) {
+    return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+      hipLaunchKernelGGL(kernel, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
+    });
+  };
   switch (kind) {
     case BK_SQ:
-      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
-        hipLaunchKernelGGL(kb_zgemm<BK_SQ>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
-      });
+      return g64 ? go_kind(kb_zgemm<BK_SQ, true>) : go_kind(kb_zgemm<BK_SQ, false>);
     case BK_GRAM:
-      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
-        hipLaunchKernelGGL(kb_zgemm<BK_GRAM>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
-      });
+      return g64 ? go_kind(kb_zgemm<BK_GRAM, true>) : go_kind(kb_zgemm<BK_GRAM, false>);
     case BK_CORR:
-      return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
-        hipLaunchKernelGGL(kb_zgemm<BK_CORR>, dim3(g), dim3(256), 0, s, step, desc, table, m, p, b);
-      });
+      return g64 ? go_kind(kb_zgemm<BK_CORR, true>) : go_kind(kb_zgemm<BK_CORR, false>);
     default:
       return hipErrorInvalidValue;
   }

@@ -63,7 +63,10 @@ struct BatchPlan {
   bool ok = true;                 // false if a launch exceeds the grid limit
 };
 
-BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, bool with_report) {
+// tile_flags: the kBatchGemm64 bit of the launch (it changes tile counts,
+// not the launch list or the table sizes)
+BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, bool with_report,
+                     int tile_flags = 0) {
   BatchPlan P;
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
@@ -72,7 +75,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
     int members = 0;
     int64_t tiles = 0;
     for (int i = 0; i < count; ++i) {
-      int64_t w = batch_tiles(kind, step, p[i].n_meas, p[i].n_mat, mixed, polar, dbl);
+      int64_t w = batch_tiles(kind, step, p[i].n_meas, p[i].n_mat, mixed, polar, dbl, tile_flags);
       if (w > 0) {
         ++members;
         tiles += w;
@@ -382,12 +385,21 @@ int timer_of(int kind) {
   return -1;
 }
 
+// Variant bits of the grouped kernels from the context's batched classes.
+int batch_variant_flags(const qpe_ctx* ctx) {
+  int f = 0;
+  if (ctx->variant[QPE_KERNEL_BATCH_GEMM][0] == 2) f |= kBatchGemm64;
+  if (ctx->variant[QPE_KERNEL_BATCH_CTRL][0] == 1) f |= kBatchCtrlInStep;
+  return f;
+}
+
 qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, unsigned flags, char* ws,
                      qpe_report* report) {
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
-  const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0);
+  const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0) |
+                 batch_variant_flags(ctx);
   hipStream_t s = ctx->stream;
-  const BatchPlan P = plan_batch(p, count, form, flags, true);
+  const BatchPlan P = plan_batch(p, count, form, flags, true, bf & kBatchGemm64);
   int32_t* tables = reinterpret_cast<int32_t*>(ws);
   InstDesc* desc = reinterpret_cast<InstDesc*>(ws + P.desc_off);
   for (int first = 0; first < count; first += kBatchChunk) {
@@ -483,6 +495,8 @@ static int variant_count(int kernel_class) {
     case QPE_KERNEL_CTRL_MIXED: return ctrl_mixed_variants();
     case QPE_KERNEL_ZGEMM: return zgemm_variants();
     case QPE_KERNEL_CTRL_F64: return ctrl_f64_variants();
+    case QPE_KERNEL_BATCH_CTRL: return 2;
+    case QPE_KERNEL_BATCH_GEMM: return 2;
   }
   return -1;
 }
@@ -500,8 +514,9 @@ QPE_API qpe_status qpe_ctx_set_variant(qpe_ctx* ctx, int kernel_class, int n_mat
   int c = variant_count(kernel_class);
   if (c < 0 || variant < 0 || variant > c) return QPE_ERR_ARG;
   if (n_mat < -1 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
+  const bool batched = kernel_class == QPE_KERNEL_BATCH_CTRL || kernel_class == QPE_KERNEL_BATCH_GEMM;
   for (int t = 0; t <= QPE_MAX_N_MAT; ++t)
-    if (n_mat < 0 || t == n_mat) ctx->variant[kernel_class][t] = variant;
+    if (batched || n_mat < 0 || t == n_mat) ctx->variant[kernel_class][t] = variant;
   return QPE_OK;
 }
 
@@ -569,6 +584,70 @@ QPE_API qpe_status qpe_autotune(qpe_ctx* ctx, const qpe_problem* problem, int fo
       }
     }
     ctx->variant[c][t] = best_v;
+    chosen[c] = best_v;
+  }
+  ctx->timing = was_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+QPE_API qpe_status qpe_autotune_batch(qpe_ctx* ctx, const qpe_problem* problems, int count, int form,
+                                      unsigned flags, void* workspace, size_t workspace_bytes, int reps,
+                                      int* chosen, double* class_ms) {
+  if (!ctx || !chosen || count < 2) return QPE_ERR_ARG;
+  if (reps < 1 || reps > 1000) return QPE_ERR_ARG;
+  qpe_status s = qpe_check_run(problems, count, form, flags, workspace, workspace_bytes, nullptr);
+  if (s != QPE_OK) return s;
+  ctx->last_error.clear();
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+  const bool mixed = form == QPE_FORM_MIXED;
+  bool uses[QPE_KERNEL_COUNT] = {};
+  for (int i = 0; i < count; ++i) {
+    uses[QPE_KERNEL_BATCH_GEMM] |= problems[i].n_meas >= 2;
+    uses[QPE_KERNEL_BATCH_CTRL] |= mixed && problems[i].n_mat >= 7;
+  }
+  if (class_ms)
+    for (int i = 0; i < QPE_KERNEL_COUNT * QPE_TUNE_MAX_VARIANTS; ++i) class_ms[i] = -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  qpe_status st = QPE_OK;
+  char* ws = static_cast<char*>(workspace);
+  for (int c = 0; c < QPE_KERNEL_COUNT && st == QPE_OK; ++c) {
+    chosen[c] = ctx->variant[c][0];
+    if (!uses[c]) continue;
+    const int nv = variant_count(c);
+    double best = 1e300;
+    int best_v = 0;
+    auto set_all = [&](int v) {
+      for (int t = 0; t <= QPE_MAX_N_MAT; ++t) ctx->variant[c][t] = v;
+    };
+    for (int v = 0; v <= nv && v < QPE_TUNE_MAX_VARIANTS && st == QPE_OK; ++v) {
+      set_all(v);
+      st = run_batch(ctx, problems, count, form, flags, ws, nullptr);  // warm-up
+      if (st != QPE_OK) break;
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = hip_fail(ctx, hipErrorUnknown, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && st == QPE_OK; ++r) st = run_batch(ctx, problems, count, form, flags, ws, nullptr);
+      if (st != QPE_OK) break;
+      hipError_t he = hipEventRecord(e1, ctx->stream);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) { st = hip_fail(ctx, he, "autotune timing"); break; }
+      const double per = double(ms) / reps;
+      if (class_ms) class_ms[c * QPE_TUNE_MAX_VARIANTS + v] = per;
+      if (per < best) {
+        best = per;
+        best_v = v;
+      }
+    }
+    set_all(best_v);
     chosen[c] = best_v;
   }
   ctx->timing = was_timing;

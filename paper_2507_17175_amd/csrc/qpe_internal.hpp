@@ -192,10 +192,20 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // Workgroups instance (n, t) contributes to launch (kind, step); 0 if it
 // takes no part. step = controlled step k, or the DFT pass index.
 // Flag bits of the grouped kernels' `bflags` argument.
-constexpr int kBatchPolar = 1, kBatchDoubling = 2;
+// kBatchGemm64: the power-chain products of operators with d >= 64 use
+// 64 x 64 tiles (32 x 32 otherwise); kBatchCtrlInStep: the d >= 128
+// controlled step uses the in-step schedule instead of the ping-pong one.
+// Neither changes the order of any sum, so results are the same bit for bit.
+constexpr int kBatchPolar = 1, kBatchDoubling = 2, kBatchGemm64 = 4, kBatchCtrlInStep = 8;
+
+// Tile edge of the grouped power-chain products of an instance with 2^t x 2^t
+// operators.
+__host__ __device__ inline int batch_gemm_tile(int t, int bflags) {
+  return ((bflags & kBatchGemm64) && t >= 6) ? 64 : kBatchGemmTile;
+}
 
 __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t, bool mixed, bool polar,
-                                               bool dbl = false) {
+                                               bool dbl = false, int bflags = 0) {
   const int64_t N = int64_t(1) << n, d = int64_t(1) << t;
   // rows a controlled step writes: the gate route's N/2 rows with bit k set,
   // or the 2^k new rows of the prefix-doubling form
@@ -209,16 +219,19 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       int h = tw_split(n);
       return cdiv((int64_t(1) << h) + (int64_t(1) << (n - h)), 256);
     }
-    case BK_SQ:
-      return (step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile) : 0;
+    case BK_SQ: {
+      const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
+      return (step >= 1 && step < n) ? T * T : 0;
+    }
     case BK_GRAM: {
       // Hermitian: the tiles on or above the diagonal (twice when split)
-      const int64_t T = cdiv(d, kBatchGemmTile);
+      const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
       return (polar && step >= 1 && step < n) ? T * (T + 1) / 2 * (gram_split(t) ? 2 : 1) : 0;
     }
-    case BK_CORR:
-      return (polar && !(mixed && t >= 5) && step >= 1 && step < n) ? cdiv(d, kBatchGemmTile) * cdiv(d, kBatchGemmTile)
-                                                                     : 0;
+    case BK_CORR: {
+      const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
+      return (polar && !(mixed && t >= 5) && step >= 1 && step < n) ? T * T : 0;
+    }
     case BK_NSPREP:
     case BK_NSUPD:
       return (polar && mixed && t >= 5 && step >= 1 && step < n) ? cdiv(d * d, kSplitTile) : 0;

@@ -40,10 +40,10 @@ EXPORTS = (
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_set_timing_mask", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
     "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
-    "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune",
+    "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune", "qpe_autotune_batch",
 )
 
-KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2}
+KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2, "batch_ctrl": 3, "batch_gemm": 4}
 TUNE_MAX_VARIANTS = 8
 
 TIMERS = {"ctrl_gemm": 0, "powers": 1, "split": 2, "qft": 3, "prob": 4, "hlayer": 5}
@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_ctx_get_variant": (st, [vp, i32, i32, ctypes.POINTER(i32)]),
             "qpe_autotune": (st, [vp, ctypes.POINTER(Problem), i32, ctypes.c_uint, vp, sz, i32,
                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+            "qpe_autotune_batch": (st, [vp, ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, vp, sz, i32,
+                                        ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
             "qpe_estimate_workspace_size": (st, [i32, ctypes.POINTER(sz)]),
             "qpe_estimate": (st, [vp, ctypes.POINTER(Problem), i32, vp, vp, sz]),
             "qpe_status_string": (ctypes.c_char_p, [i32]),
@@ -508,6 +510,26 @@ class Runner:
                          self.report_buf.data_ptr() if self.report_buf is not None else None),
                "qpe_run", self.ctx.handle)
         return self.probs
+
+    def autotune(self, reps: int = 2) -> Dict:
+        """Batched runs (count >= 2): time every variant of the batched kernel
+        classes over whole runs of this batch and keep the fastest in the
+        context (qpe_autotune_batch). Synchronises; overwrites the outputs."""
+        L = load_library()
+        self.ctx.bind_current_stream()
+        chosen = (ctypes.c_int * len(KERNEL_CLASSES))()
+        ms = (ctypes.c_double * (len(KERNEL_CLASSES) * TUNE_MAX_VARIANTS))()
+        _check(L.qpe_autotune_batch(self.ctx.handle, self.arr, self.count, self.form, self.flags,
+                                    self.workspace.data_ptr(), self.workspace.numel(), int(reps), chosen, ms),
+               "qpe_autotune_batch", self.ctx.handle)
+        out = {"chosen": {}, "ms_per_batch": {}}
+        for name, c in KERNEL_CLASSES.items():
+            tried = [round(ms[c * TUNE_MAX_VARIANTS + v], 4) for v in range(TUNE_MAX_VARIANTS)
+                     if ms[c * TUNE_MAX_VARIANTS + v] >= 0]
+            if tried:
+                out["chosen"][name] = chosen[c]
+                out["ms_per_batch"][name] = tried
+        return out
 
     def reports(self):
         torch.cuda.current_stream(self.dev).synchronize()

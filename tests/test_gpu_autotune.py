@@ -43,3 +43,56 @@ def test_autotune_keeps_results(qpe, form, n, t):
         assert table.get(name, {}).get(t, 0) == v
     for name in qpe.KERNEL_CLASSES:
         ctx.set_variant(name, 0)
+
+
+def _batch_items(seed):
+    # uneven sizes on both sides of the d >= 64 tile switch and of the d >= 128
+    # controlled-step class, and one d = 1024 instance (Gram split in K halves)
+    shapes = [(9, 3), (10, 6), (8, 7), (11, 8), (7, 5), (12, 6), (9, 8), (6, 10)]
+    rng = np.random.default_rng(seed)
+    probs = [make_problem(n, t, rng) for n, t in shapes]
+    return probs, [(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas) for p in probs]
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_variants_bitwise(qpe, form):
+    probs, items = _batch_items(61)
+    run = qpe.Runner(items, form=form)
+    ctx = run.ctx
+    ref = None
+    try:
+        for vc in (0, 1, 2):
+            for vg in (0, 1, 2):
+                ctx.set_variant("batch_ctrl", vc)
+                ctx.set_variant("batch_gemm", vg)
+                out = [P.cpu().numpy().copy() for P in run()]
+                if ref is None:
+                    ref = out
+                for i, (a, b) in enumerate(zip(out, ref)):
+                    assert np.array_equal(a, b), (form, vc, vg, i)
+    finally:
+        ctx.set_variant("batch_ctrl", 0)
+        ctx.set_variant("batch_gemm", 0)
+    # and the batch equals the single runs, bit for bit
+    for (U, psi, n), P in zip(items, ref):
+        assert np.array_equal(qpe.run(U, psi, n, form=form).cpu().numpy(), P)
+
+
+def test_autotune_batch(qpe):
+    probs, items = _batch_items(62)
+    run = qpe.Runner(items, form="mixed")
+    before = [P.cpu().numpy().copy() for P in run()]
+    ctx = run.ctx
+    try:
+        res = run.autotune(reps=1)
+        assert set(res["chosen"]) == {"batch_ctrl", "batch_gemm"}
+        for name, v in res["chosen"].items():
+            assert 0 <= v <= 2
+            assert ctx.get_variant(name, 0) == v and ctx.get_variant(name, 9) == v
+            assert len(res["ms_per_batch"][name]) == 3 and all(m > 0 for m in res["ms_per_batch"][name])
+        after = [P.cpu().numpy() for P in run()]
+        for a, b in zip(after, before):
+            assert np.array_equal(a, b)
+    finally:
+        ctx.set_variant("batch_ctrl", 0)
+        ctx.set_variant("batch_gemm", 0)
