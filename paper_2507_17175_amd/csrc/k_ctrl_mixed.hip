@@ -507,7 +507,7 @@ template <int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                               const uint16_t* __restrict__ planes, int n, int t, int k,
                                               uint64_t pmask, int tile_m, int tile_n) {
-  constexpr int NT = 512, NG = 256;  // threads per workgroup, per group
+  constexpr int NG = 256;  // threads per group (half of the 512-thread workgroup)
   static_assert(WM == 2 && WN == 4, "a group is one row half of the tile");
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;

@@ -43,7 +43,8 @@ __device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restr
     }
     // Rolled for larger d: unrolling lets the compiler hoist all d*d
     // operator entries out of the row loop into registers, which spills.
-#pragma unroll(D >= 8 ? 1 : D)
+    constexpr int kRowUnroll = D >= 8 ? 1 : D;
+#pragma unroll kRowUnroll
     for (int r = 0; r < D; ++r) {
       R yr = R(0), yi = R(0);
 #pragma unroll

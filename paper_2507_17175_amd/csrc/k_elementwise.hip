@@ -200,7 +200,7 @@ __device__ inline void report_block(const double* __restrict__ prob, int n, cons
   __syncthreads();
   if (bad) atomicOr(&any_bad, 1);
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if (int(threadIdx.x) < w) {
       red[0][threadIdx.x] += red[0][threadIdx.x + w];
       red[1][threadIdx.x] += red[1][threadIdx.x + w];
     }

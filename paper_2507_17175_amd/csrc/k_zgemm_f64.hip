@@ -45,8 +45,6 @@ __device__ inline int2 xcd_tile_of(int w, int tiles_m, int tiles_n) {
   return make_int2(w / tiles_n, w % tiles_n);
 }
 
-__device__ inline int2 xcd_tile(int tiles_m, int tiles_n) { return xcd_tile_of(blockIdx.x, tiles_m, tiles_n); }
-
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs& g, int tile_m, int tile_n) {
   constexpr int kThreads = 64 * WM * WN;
