@@ -125,3 +125,23 @@ def test_graph_replay_single_instance(qpe, flags):
         assert np.array_equal(host(out[0]), eager), rep
     ref = O.qpe_probs(p.U, p.psi, p.n_meas)
     assert float(np.abs(eager - ref).max()) < 1e-6
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_beyond_4096_instances(qpe, form):
+    """More than 4096 members in a launch table: the instance lookup of the
+    grouped kernels takes its third sampling round. 4500 tiny instances
+    (n <= 3, d <= 4) against the oracle, a sample also against single runs."""
+    rng = np.random.default_rng(4500)
+    probs = [make_problem(1 + int(rng.integers(3)), int(rng.integers(3)), rng) for _ in range(4500)]
+    say("batch of", len(probs), "tiny instances", form)
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    out = qpe.run_batch(items, form)
+    tol = 1e-6 if form == "mixed" else 1e-12
+    worst = 0.0
+    for p, P in zip(probs, out):
+        worst = max(worst, float(np.abs(host(P) - O.qpe_probs(p.U, p.psi, p.n_meas)).max()))
+    assert worst <= tol, worst
+    for i in range(0, len(probs), 499):
+        U, psi, n = items[i]
+        assert np.array_equal(host(qpe.run(U, psi, n, form=form)), host(out[i])), i
