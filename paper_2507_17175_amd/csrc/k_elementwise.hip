@@ -169,6 +169,8 @@ __device__ inline void prob_rows(const T* __restrict__ X, double* __restrict__ p
   double acc = 0.0;
   if (p < N) {
     const T* row = X + p * d;
+    // unrolled so that several loads are in flight; the sum keeps its order
+#pragma unroll 4
     for (int c = c0; c < d; c += G) {
       T v = row[c];
       double re = double(v.x), im = double(v.y);
