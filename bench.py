@@ -91,13 +91,28 @@ def bench_batch(a, qpe, torch, config_problems):
     el = time.perf_counter() - t0
     timing = run.ctx.read_timing()
     run.ctx.reset_timing()
+    run.ctx.set_timing_mask([])  # no event records inside the captured graph
     graph = qpe.CapturedRun(run)
     t0 = time.perf_counter()
     for _ in range(a.steps):
         graph()
     torch.cuda.synchronize()
     el_g = time.perf_counter() - t0
+    run.ctx.set_timing_mask(None)
     rep = run.reports()
+    P_mixed = [P.cpu().numpy() for P in run.probs]
+    # the same batch in the FP64 form (replayed graph), beside it
+    run64 = qpe.Runner(items, form="fp64")
+    run64()
+    torch.cuda.synchronize()
+    graph64 = qpe.CapturedRun(run64)
+    steps64 = max(2, a.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps64):
+        graph64()
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    dP = max(float(np.abs(P64.cpu().numpy() - Pm).max()) for P64, Pm in zip(run64.probs, P_mixed))
     count = len(probs)
     flops = sum(4.0 * p.n_meas * (1 << p.n_meas) * (1 << p.n_mat) ** 2 for p in probs)
     g_cnt, g_ms = timing["ctrl_gemm"]
@@ -120,6 +135,10 @@ def bench_batch(a, qpe, torch, config_problems):
                       for k, (c, ms) in timing.items()},
         "reports": {"flags_nonzero": int(np.count_nonzero(rep["flags"])),
                     "max_abs_prob_sum_minus_1": float(np.abs(rep["prob_sum"] - 1.0).max())},
+        "fp64_form": {"circuits_per_s": round(count * steps64 / el64, 2),
+                      "ms_per_step": round(1e3 * el64 / steps64, 3), "steps": steps64},
+        "mixed_over_fp64": round((count * a.steps / el_g) / (count * steps64 / el64), 3),
+        "max_abs_dP_mixed_vs_fp64": dP,
     }
     print(json.dumps(out), flush=True)
     return 0
