@@ -91,14 +91,12 @@ def bench_batch(a, qpe, torch, config_problems):
     el = time.perf_counter() - t0
     timing = run.ctx.read_timing()
     run.ctx.reset_timing()
-    run.ctx.set_timing_mask([])  # no event records inside the captured graph
     graph = qpe.CapturedRun(run)
     t0 = time.perf_counter()
     for _ in range(a.steps):
         graph()
     torch.cuda.synchronize()
     el_g = time.perf_counter() - t0
-    run.ctx.set_timing_mask(None)
     rep = run.reports()
     P_mixed = [P.cpu().numpy() for P in run.probs]
     # the same batch in the FP64 form (replayed graph), beside it

@@ -220,6 +220,7 @@ class Context:
         mask = (1 << len(TIMERS)) - 1 if classes is None else sum(1 << TIMERS[c] for c in classes)
         _check(load_library().qpe_ctx_set_timing_mask(self.handle, ctypes.c_uint(mask)), "qpe_ctx_set_timing_mask",
                self.handle)
+        self.timing_classes = None if classes is None else list(classes)
 
     def reset_timing(self) -> None:
         _check(load_library().qpe_ctx_reset_timing(self.handle), "qpe_ctx_reset_timing")
@@ -560,10 +561,16 @@ class CapturedRun:
                 runner()
         torch.cuda.current_stream(runner.dev).wait_stream(side)
         torch.cuda.synchronize(runner.dev)
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            runner()
-        torch.cuda.synchronize(runner.dev)
+        # the per-kernel timers record events, which a graph must not hold
+        saved = getattr(runner.ctx, "timing_classes", None)
+        runner.ctx.set_timing_mask([])
+        try:
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                runner()
+            torch.cuda.synchronize(runner.dev)
+        finally:
+            runner.ctx.set_timing_mask(saved)
 
     def __call__(self) -> List[torch.Tensor]:
         self.graph.replay()

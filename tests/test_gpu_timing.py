@@ -42,3 +42,22 @@ def test_timing_mask(qpe):
     ctx.reset_timing()
     run()
     assert ctx.read_timing()["powers"][0] > 0
+
+
+def test_capture_records_no_timer_events(qpe):
+    p = make_problem(9, 6, np.random.default_rng(5))
+    run = qpe.Runner([(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas)], form="mixed")
+    ctx = run.ctx
+    ctx.enable_timing(1024)
+    ctx.set_timing_mask(None)
+    ref = run()[0].cpu().numpy().copy()
+    graph = qpe.CapturedRun(run)
+    ctx.reset_timing()
+    for _ in range(3):
+        out = graph()[0].cpu().numpy()
+        assert np.array_equal(out, ref)
+    tm = ctx.read_timing()
+    assert all(v[0] == 0 for v in tm.values()), tm  # the graph holds no event records
+    run()  # eager timing works again, every class
+    tm = ctx.read_timing()
+    assert tm["ctrl_gemm"][0] == p.n_meas and tm["qft"][0] > 0
