@@ -100,8 +100,14 @@ __device__ __forceinline__ T twiddled(R yr, R yi, double2 w) {
   return o;
 }
 
-// Largest LDS exchange buffer of a pass (R1 = R2 = 16): 16 x 16 x 16 points.
+// Largest LDS exchange buffer of a pass with one DFT row per thread
+// (R1 = R2 = 16): 16 x 16 x 16 points.
 constexpr int kQftLds = 4096;
+
+// DFT rows per thread of a radix-256 pass: two for complex64, so that a
+// workgroup covers 32 elements (256-byte row runs; 14 % faster at 2^26
+// amplitudes); one for complex128, where it did not pay.
+template <typename T> constexpr int kQftRowsPerThread256 = sizeof(T) == 8 ? 2 : 1;
 
 // Workgroup `block` of one pass; L: LDS scratch of R1 R2 E points. EM > 1
 // (R2 > 1 only): each thread takes EM of the R2 DFT rows of phase A, so a
@@ -115,8 +121,8 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
   typedef typename Real<T>::type R;
   static_assert(EM == 1 || R2 > 1, "the in-register pass takes one element per thread");
   constexpr int E = EM * kThreads / R2;  // elements per workgroup
-  // the grouped kernel's buffer holds kQftLds points, enough for EM = 1
-  static_assert(EM > 1 || R1 * R2 * E <= kQftLds, "LDS exchange buffer");
+  // the grouped kernel's buffer holds EM kQftLds points
+  static_assert(R1 * R2 * E <= EM * kQftLds, "LDS exchange buffer");
   constexpr int L1 = Log2<R1>::v, L2 = Log2<R2>::v;
 
   const int bq_log = n - bits_before;        // rows per block (log2)
@@ -256,7 +262,8 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __restrict__ desc,
                                                    const int32_t* __restrict__ table, int bflags, int64_t tile0) {
   constexpr bool mixed = sizeof(T) == 8;
-  __shared__ T L[kQftLds];
+  // complex64 radix-256 passes take 32 elements per workgroup, as single runs do
+  __shared__ T L[mixed ? 2 * kQftLds : kQftLds];
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
@@ -279,16 +286,14 @@ __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __r
     case 5: qft_tile<T, 16, 2>(b0, b1, g, n, t, 5, before, hi, lo, h, local, L); break;
     case 6: qft_tile<T, 16, 4>(b0, b1, g, n, t, 6, before, hi, lo, h, local, L); break;
     case 7: qft_tile<T, 16, 8>(b0, b1, g, n, t, 7, before, hi, lo, h, local, L); break;
-    case 8: qft_tile<T, 16, 16>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L); break;
+    case 8: qft_tile<T, 16, 16, kQftRowsPerThread256<T>>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L); break;
   }
 }
 
 template <typename T, int R1, int R2>
 hipError_t go(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
               const double2* lo, int h, hipStream_t s) {
-  // complex64 radix-256 passes: two DFT rows per thread, so a workgroup
-  // covers 32 elements (256-byte row runs; 14 % faster at 2^26 amplitudes)
-  constexpr int EM = (R2 == 16 && sizeof(T) == 8) ? 2 : 1;
+  constexpr int EM = R2 == 16 ? kQftRowsPerThread256<T> : 1;
   constexpr int E = EM * kThreads / R2;
   int64_t total_e = int64_t(1) << (n + t - pb);
   int64_t grid = (total_e + E - 1) / E;

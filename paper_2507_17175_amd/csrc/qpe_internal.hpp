@@ -260,7 +260,9 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       if (step >= pl.npass) return 0;
       int b = pl.bits[step];
       int r2 = b > 4 ? (1 << (b - 4)) : 1;
-      return cdiv((N * d) >> b, 256 / r2);
+      // elements per workgroup: 256 / r2, twice that for complex64 radix 256
+      int e = (256 / r2) * ((mixed && b == 8) ? 2 : 1);
+      return cdiv((N * d) >> b, e);
     }
     case BK_PROB: {
       int64_t G = d < 64 ? d : 64;
