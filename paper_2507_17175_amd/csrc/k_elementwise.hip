@@ -181,19 +181,29 @@ __device__ inline void prob_rows(const T* __restrict__ X, double* __restrict__ p
   if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
 }
 
-// Report: prob_sum, ||psi||^2, the defect and the flags, by one block.
+// Report: prob_sum, ||psi||^2, the defect and the flags, by one block. With
+// `part` (nparts pairs: partial sum, non-finite flag, from k_report_partial)
+// it adds the partial sums instead of reading the 2^n probabilities itself.
 __device__ inline void report_block(const double* __restrict__ prob, int n, const double2* __restrict__ psi, int t,
-                                    const unsigned long long* __restrict__ defect_bits, double* __restrict__ report) {
+                                    const unsigned long long* __restrict__ defect_bits, double* __restrict__ report,
+                                    const double* __restrict__ part = nullptr, int nparts = 0) {
   __shared__ double red[2][kThreads];
   __shared__ int any_bad;
   const int64_t N = int64_t(1) << n;
   const int d = 1 << t;
   double s = 0.0, q = 0.0;
   bool bad = false;
-  for (int64_t i = threadIdx.x; i < N; i += kThreads) {
-    double v = prob[i];
-    bad |= !(v == v) || v > 1e300 || v < -1e300;
-    s += v;
+  if (part) {
+    for (int i = threadIdx.x; i < nparts; i += kThreads) {
+      s += part[2 * i];
+      bad |= part[2 * i + 1] != 0.0;
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < N; i += kThreads) {
+      double v = prob[i];
+      bad |= !(v == v) || v > 1e300 || v < -1e300;
+      s += v;
+    }
   }
   for (int i = threadIdx.x; i < d; i += kThreads) q += psi[i].x * psi[i].x + psi[i].y * psi[i].y;
   red[0][threadIdx.x] = s;
@@ -377,8 +387,41 @@ __global__ void __launch_bounds__(kThreads) k_gather_state(const T* __restrict__
 __global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
                                                      const double2* __restrict__ psi, int t,
                                                      const unsigned long long* __restrict__ defect_bits,
-                                                     double* __restrict__ report) {
-  report_block(prob, n, psi, t, defect_bits, report);
+                                                     double* __restrict__ report, const double* __restrict__ part,
+                                                     int nparts) {
+  report_block(prob, n, psi, t, defect_bits, report, part, nparts);
+}
+
+// First stage of the report for large registers: block b sums the
+// probabilities [b C, (b + 1) C), C = kReportChunk, in a fixed order (a
+// strided pass per thread, then a fixed tree) and flags non-finite values.
+constexpr int kReportChunk = 4096;
+
+__global__ void __launch_bounds__(kThreads) k_report_partial(const double* __restrict__ prob,
+                                                             double* __restrict__ part) {
+  __shared__ double red[kThreads];
+  __shared__ int any_bad;
+  const double* p = prob + int64_t(blockIdx.x) * kReportChunk;
+  double s = 0.0;
+  bool bad = false;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < kReportChunk; i += kThreads) {
+    const double v = p[i];
+    bad |= !(v == v) || v > 1e300 || v < -1e300;
+    s += v;
+  }
+  red[threadIdx.x] = s;
+  if (threadIdx.x == 0) any_bad = 0;
+  __syncthreads();
+  if (bad) atomicOr(&any_bad, 1);
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0];
+    part[2 * blockIdx.x + 1] = any_bad ? 1.0 : 0.0;
+  }
 }
 
 // After a stand-alone controlled step (whole state in buf0, updated rows
@@ -671,9 +714,15 @@ hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t
 }
 
 hipError_t launch_report(const double* prob, int n, const double2* psi, int t, const unsigned long long* defect_bits,
-                         void* report, hipStream_t s) {
+                         void* report, double* part, hipStream_t s) {
+  const int64_t N = int64_t(1) << n;
+  int nparts = 0;
+  if (part && N >= 4 * kReportChunk) {
+    nparts = int(N / kReportChunk);
+    hipLaunchKernelGGL(k_report_partial, dim3(nparts), dim3(kThreads), 0, s, prob, part);
+  }
   hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, s, prob, n, psi, t, defect_bits,
-                     static_cast<double*>(report));
+                     static_cast<double*>(report), nparts ? part : nullptr, nparts);
   return hipGetLastError();
 }
 

@@ -362,7 +362,9 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, !dbl, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
                                  reinterpret_cast<double2*>(ws + L.tw_lo));
   if (st != QPE_OK) return st;
-  if (report) QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, s));
+  // the second state buffer is free once the inverse QFT has read it
+  if (report)
+    QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, static_cast<double*>(s1), s));
   return QPE_OK;
 }
 

@@ -338,8 +338,10 @@ hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsi
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
                        hipStream_t s);
+// part (optional): device scratch of 2^n / 256 bytes (16-byte aligned) for
+// the partial sums of a two-stage sum when 2^n >= 16384.
 hipError_t launch_report(const double* prob, int n, const double2* psi, int t,
-                         const unsigned long long* defect_bits, void* report, hipStream_t s);
+                         const unsigned long long* defect_bits, void* report, double* part, hipStream_t s);
 // Final statevector in outcome order: out[m][r] = scale * X[p][r] where row
 // position p of the DFT output holds outcome m (prob_index(p) = m).
 hipError_t launch_gather_state(bool mixed, const void* X, void* out, int n, int t, const DftPlan& plan, double scale,
