@@ -1,10 +1,13 @@
 // Controlled step (Fig. 1, controlled U^(2^k)) for target registers of at
 // most 4 qubits (d <= 16). A d x d operator is too small to fill a matrix
 // core tile, and the step is bound by HBM traffic, so each thread owns one
-// gathered state row: it loads the d amplitudes, forms s <- V s with the
-// operator broadcast from LDS, and writes the row to the other ping-pong
-// buffer. FP64 form: complex128 state, FP64 arithmetic. Mixed form:
-// complex64 state, the operator rounded once to FP32, FP32 FMAs.
+// gathered state row: it forms s <- V s with the operator broadcast from
+// LDS. A workgroup moves its 256 rows between HBM and LDS with consecutive
+// lanes on consecutive amplitudes (a thread reading its own row straight
+// from HBM would touch a different cache line per lane), and the result goes
+// to the other ping-pong buffer the same way. FP64 form: complex128 state,
+// FP64 arithmetic. Mixed form: complex64 state, the operator rounded once to
+// FP32, FP32 FMAs.
 #include "qpe_internal.hpp"
 
 namespace qpe {
@@ -17,39 +20,42 @@ template <typename T> struct Real;
 template <> struct Real<float2> { typedef float type; };
 template <> struct Real<double2> { typedef double type; };
 
-// Rows i in [i0, i1) (stride) of the gathered set of step k.
+// Gathered rows [i0, min(i0 + kThreads, M)) of step k: thread r computes row
+// i0 + r from LDS; the tile moves in and out with element e = tid + q
+// kThreads (row e / D, amplitude e % D), rows padded to D + 1 amplitudes.
 template <typename T, int D>
-__device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restrict__ buf1,
-                                                const double2* __restrict__ V, int k, uint64_t pmask, int64_t i0,
-                                                int64_t i1, int64_t stride) {
+__device__ __forceinline__ void ctrl_small_tile(T* __restrict__ buf0, T* __restrict__ buf1, const T* __restrict__ Vs,
+                                                int k, uint64_t pmask, int64_t i0, int64_t M, T* __restrict__ X) {
   typedef typename Real<T>::type R;
-  __shared__ R Vre[D * D], Vim[D * D];
-  for (int e = threadIdx.x; e < D * D; e += kThreads) {
-    Vre[e] = R(V[e].x);
-    Vim[e] = R(V[e].y);
+  constexpr int P = D + 1;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
+    const int64_t i = i0 + row;
+    if (i < M) {
+      const int64_t j = step_row(i, k, pmask);
+      X[row * P + c] = ((src_buffer(j, pmask) ? buf1 : buf0) + j * D)[c];
+    }
   }
   __syncthreads();
-  for (int64_t i = i0; i < i1; i += stride) {
-    int64_t j = step_row(i, k, pmask);
-    int p = src_buffer(j, pmask);
-    const T* src = (p ? buf1 : buf0) + j * D;
-    T* dst = (p ? buf0 : buf1) + j * D;
+  if (i0 + threadIdx.x < M) {
+    T* x = X + threadIdx.x * P;
     R xr[D], xi[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      T v = src[c];
+      const T v = x[c];
       xr[c] = v.x;
       xi[c] = v.y;
     }
-    // Rolled for larger d: unrolling lets the compiler hoist all d*d
-    // operator entries out of the row loop into registers, which spills.
-    constexpr int kRowUnroll = D >= 8 ? 1 : D;
-#pragma unroll kRowUnroll
+    // Rolled: unrolling lets the compiler hoist all d*d operator entries
+    // out of the row loop into registers, which spills.
+#pragma unroll 1
     for (int r = 0; r < D; ++r) {
       R yr = R(0), yi = R(0);
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        R vr = Vre[r * D + c], vi = Vim[r * D + c];
+        const T v = Vs[r * D + c];
+        const R vr = v.x, vi = v.y;
         yr = fma(vr, xr[c], yr);
         yr = fma(-vi, xi[c], yr);
         yi = fma(vr, xi[c], yi);
@@ -58,7 +64,82 @@ __device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restr
       T o;
       o.x = yr;
       o.y = yi;
-      dst[r] = o;
+      x[r] = o;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
+    const int64_t i = i0 + row;
+    if (i < M) {
+      const int64_t j = step_row(i, k, pmask);
+      ((src_buffer(j, pmask) ? buf0 : buf1) + j * D)[c] = X[row * P + c];
+    }
+  }
+}
+
+// The operator rounded to the state's type, into LDS.
+template <typename T, int D>
+__device__ __forceinline__ void load_operator(const double2* __restrict__ V, T* __restrict__ Vs) {
+  typedef typename Real<T>::type R;
+  for (int e = threadIdx.x; e < D * D; e += kThreads) {
+    T v;
+    v.x = R(V[e].x);
+    v.y = R(V[e].y);
+    Vs[e] = v;
+  }
+  __syncthreads();
+}
+
+// Rows [0, M) in tiles of kThreads, tile b, b + stride, ...; Vs is LDS of
+// D * D elements. With STAGE and D >= 8 the rows go through X (LDS of
+// kThreads * (D + 1) elements); otherwise each thread reads and writes its own
+// row directly, which costs less for rows of at most four amplitudes (32 or
+// 64 bytes), where the LDS round trip saves nothing.
+template <typename T, int D, bool STAGE>
+__device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restrict__ buf1,
+                                                const double2* __restrict__ V, int k, uint64_t pmask, int64_t tile0,
+                                                int64_t M, int64_t stride, T* __restrict__ Vs, T* __restrict__ X) {
+  load_operator<T, D>(V, Vs);
+  if constexpr (STAGE && D >= 8) {
+    for (int64_t b = tile0; b * kThreads < M; b += stride) {
+      ctrl_small_tile<T, D>(buf0, buf1, Vs, k, pmask, b * kThreads, M, X);
+      __syncthreads();
+    }
+  } else {
+    typedef typename Real<T>::type R;
+    for (int64_t i = tile0 * kThreads + threadIdx.x; i < M; i += stride * kThreads) {
+      const int64_t j = step_row(i, k, pmask);
+      const int p = src_buffer(j, pmask);
+      const T* src = (p ? buf1 : buf0) + j * D;
+      T* dst = (p ? buf0 : buf1) + j * D;
+      R xr[D], xi[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T v = src[c];
+        xr[c] = v.x;
+        xi[c] = v.y;
+      }
+      // rolled for larger d, as in the staged tile
+      constexpr int kRowUnroll = D >= 8 ? 1 : D;
+#pragma unroll kRowUnroll
+      for (int r = 0; r < D; ++r) {
+        R yr = R(0), yi = R(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const T v = Vs[r * D + c];
+          const R vr = v.x, vi = v.y;
+          yr = fma(vr, xr[c], yr);
+          yr = fma(-vi, xi[c], yr);
+          yi = fma(vr, xi[c], yi);
+          yi = fma(vi, xr[c], yi);
+        }
+        T o;
+        o.x = yr;
+        o.y = yi;
+        dst[r] = o;
+      }
     }
   }
 }
@@ -66,14 +147,17 @@ __device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restr
 template <typename T, int D>
 __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T* __restrict__ buf1,
                                                          const double2* __restrict__ V, int n, int k, uint64_t pmask) {
+  __shared__ T Vs[D * D];
+  __shared__ T X[D >= 8 ? kThreads * (D + 1) : 1];
   const int64_t M = int64_t(1) << (n - 1);
-  ctrl_small_rows<T, D>(buf0, buf1, V, k, pmask, blockIdx.x * int64_t(kThreads) + threadIdx.x, M,
-                        int64_t(gridDim.x) * kThreads);
+  ctrl_small_rows<T, D, true>(buf0, buf1, V, k, pmask, blockIdx.x, M, gridDim.x, Vs, X);
 }
 
 // Grouped controlled step k over the d <= 16 instances of a launch table:
-// 256 gathered rows per workgroup.
-template <typename T>
+// 256 gathered rows per workgroup. STAGE (LDS staging for d = 8, 16) is
+// launched only when such instances take part: its LDS tile would otherwise
+// only lower the occupancy of the d <= 4 rows.
+template <typename T, bool STAGE>
 __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDesc* __restrict__ desc,
                                                           const int32_t* __restrict__ table, int bflags,
                                                           int64_t tile0) {
@@ -90,13 +174,15 @@ __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDe
   T* b1 = dbl ? b0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<T*>(D.ws + L.state1);
   const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
   const int64_t M = int64_t(1) << (dbl ? step : D.n - 1);
-  const int64_t i0 = local * kThreads + threadIdx.x;
+  constexpr int64_t kOnce = int64_t(1) << 40;  // one tile per workgroup
+  __shared__ T Vs[16 * 16];
+  __shared__ T X[STAGE ? kThreads * 17 : 1];
   switch (D.t) {
-    case 0: ctrl_small_rows<T, 1>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
-    case 1: ctrl_small_rows<T, 2>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
-    case 2: ctrl_small_rows<T, 4>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
-    case 3: ctrl_small_rows<T, 8>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
-    case 4: ctrl_small_rows<T, 16>(b0, b1, V, step, pmask, i0, M, int64_t(1) << 62); break;
+    case 0: ctrl_small_rows<T, 1, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
+    case 1: ctrl_small_rows<T, 2, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
+    case 2: ctrl_small_rows<T, 4, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
+    case 3: ctrl_small_rows<T, 8, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
+    case 4: ctrl_small_rows<T, 16, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
   }
 }
 
@@ -131,12 +217,16 @@ hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* 
 }
 
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                                   int bflags, hipStream_t s) {
+                                   bool stage, int bflags, hipStream_t s) {
   return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
-    if (mixed)
-      hipLaunchKernelGGL(kb_ctrl_small<float2>, dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+    if (mixed && stage)
+      hipLaunchKernelGGL((kb_ctrl_small<float2, true>), dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+    else if (mixed)
+      hipLaunchKernelGGL((kb_ctrl_small<float2, false>), dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+    else if (stage)
+      hipLaunchKernelGGL((kb_ctrl_small<double2, true>), dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
     else
-      hipLaunchKernelGGL(kb_ctrl_small<double2>, dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
+      hipLaunchKernelGGL((kb_ctrl_small<double2, false>), dim3(g), dim3(kThreads), 0, s, step, desc, table, bflags, b);
   });
 }
 

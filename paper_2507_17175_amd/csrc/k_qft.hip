@@ -104,10 +104,10 @@ __device__ __forceinline__ T twiddled(R yr, R yi, double2 w) {
 // (R1 = R2 = 16): 16 x 16 x 16 points.
 constexpr int kQftLds = 4096;
 
-// DFT rows per thread of a radix-256 pass: two for complex64, so that a
-// workgroup covers 32 elements (256-byte row runs; 14 % faster at 2^26
-// amplitudes); one for complex128, where it did not pay.
-template <typename T> constexpr int kQftRowsPerThread256 = sizeof(T) == 8 ? 2 : 1;
+// DFT rows per thread of a radix-256 pass (qft_two_rows): two for complex64
+// passes of 32 elements or more, so that a workgroup covers 32 elements
+// (256-byte row runs; 14 % faster at 2^26 amplitudes); one for complex128,
+// where it did not pay.
 
 // Workgroup `block` of one pass; L: LDS scratch of R1 R2 E points. EM > 1
 // (R2 > 1 only): each thread takes EM of the R2 DFT rows of phase A, so a
@@ -258,12 +258,13 @@ __global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, con
 // Grouped pass `pass` over the instances of a launch table: each instance
 // runs its own schedule (make_dft_plan of its n), so the radix is chosen
 // per workgroup.
-template <typename T>
+// WIDE: some instance of the launch takes two rows per thread in this pass
+// (the LDS buffer then holds twice the points).
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __restrict__ desc,
                                                    const int32_t* __restrict__ table, int bflags, int64_t tile0) {
   constexpr bool mixed = sizeof(T) == 8;
-  // complex64 radix-256 passes take 32 elements per workgroup, as single runs do
-  __shared__ T L[mixed ? 2 * kQftLds : kQftLds];
+  __shared__ T L[WIDE ? 2 * kQftLds : kQftLds];
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
@@ -286,14 +287,18 @@ __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __r
     case 5: qft_tile<T, 16, 2>(b0, b1, g, n, t, 5, before, hi, lo, h, local, L); break;
     case 6: qft_tile<T, 16, 4>(b0, b1, g, n, t, 6, before, hi, lo, h, local, L); break;
     case 7: qft_tile<T, 16, 8>(b0, b1, g, n, t, 7, before, hi, lo, h, local, L); break;
-    case 8: qft_tile<T, 16, 16, kQftRowsPerThread256<T>>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L); break;
+    case 8:
+      if (WIDE && qft_two_rows(mixed, 8, n, t))
+        qft_tile<T, 16, 16, 2>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L);
+      else
+        qft_tile<T, 16, 16, 1>(b0, b1, g, n, t, 8, before, hi, lo, h, local, L);
+      break;
   }
 }
 
-template <typename T, int R1, int R2>
+template <typename T, int R1, int R2, int EM = 1>
 hipError_t go(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
               const double2* lo, int h, hipStream_t s) {
-  constexpr int EM = R2 == 16 ? kQftRowsPerThread256<T> : 1;
   constexpr int E = EM * kThreads / R2;
   int64_t total_e = int64_t(1) << (n + t - pb);
   int64_t grid = (total_e + E - 1) / E;
@@ -313,7 +318,9 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
     case 5: return go<T, 16, 2>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
     case 6: return go<T, 16, 4>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
     case 7: return go<T, 16, 8>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
-    case 8: return go<T, 16, 16>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+    case 8:
+      if (qft_two_rows(sizeof(T) == 8, 8, n, t)) return go<T, 16, 16, 2>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
+      return go<T, 16, 16, 1>(b0, b1, gather, n, t, pb, bb, hi, lo, h, s);
   }
   return hipErrorInvalidValue;
 }
@@ -321,12 +328,14 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
 }  // namespace
 
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                            int bflags, hipStream_t s) {
+                            bool wide, int bflags, hipStream_t s) {
   return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
-    if (mixed)
-      hipLaunchKernelGGL(kb_qft<float2>, dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+    if (mixed && wide)
+      hipLaunchKernelGGL((kb_qft<float2, true>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+    else if (mixed)
+      hipLaunchKernelGGL((kb_qft<float2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
     else
-      hipLaunchKernelGGL(kb_qft<double2>, dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+      hipLaunchKernelGGL((kb_qft<double2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
   });
 }
 

@@ -415,6 +415,8 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
     }
     QPE_HIP(ctx, launch_batch_descs(desc, ws, chunk, first, c, s));
   }
+  bool stage_small = false;  // an instance with d = 8 or 16 takes the small controlled step
+  for (int i = 0; i < count; ++i) stage_small |= p[i].n_mat == 3 || p[i].n_mat == 4;
   const int nl = int(P.launches.size());
   for (int first = 0; first < nl; first += kBatchLaunchChunk) {
     int c = nl - first < kBatchLaunchChunk ? nl - first : kBatchLaunchChunk;
@@ -432,7 +434,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
         QPE_HIP(ctx, launch_batch_zgemm(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
         break;
       case BK_CTRL_SMALL:
-        QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, bf, s));
+        QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, stage_small, bf, s));
         break;
       case BK_CTRL_M32:
       case BK_CTRL_M64:
@@ -445,9 +447,15 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_CTRL_F64:
         QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, bf, s));
         break;
-      case BK_QFT:
-        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, bf, s));
+      case BK_QFT: {
+        bool wide = false;  // an instance takes two rows per thread in this pass
+        for (int i = 0; i < count && !wide; ++i) {
+          const DftPlan pl = make_dft_plan(p[i].n_meas);
+          wide = L.step < pl.npass && qft_two_rows(mixed, pl.bits[L.step], p[i].n_meas, p[i].n_mat);
+        }
+        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, wide, bf, s));
         break;
+      }
       default:
         QPE_HIP(ctx, launch_batch_elementwise(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
     }

@@ -25,6 +25,14 @@ struct DftPlan {
   int bits[8];
 };
 
+// Radix-256 passes over the complex64 state take two DFT rows per thread (a
+// workgroup covers 32 consecutive elements instead of 16) when the pass has
+// at least 32 elements (2^(n + t - 8)); below that the second row only halves
+// the number of threads with work.
+__host__ __device__ inline bool qft_two_rows(bool mixed, int pass_bits, int n, int t) {
+  return mixed && pass_bits == 8 && n + t >= 13;
+}
+
 // Passes of at most 8 bits (radix 256 = 16 x 16 through LDS), balanced.
 __host__ __device__ inline DftPlan make_dft_plan(int n) {
   DftPlan p{};
@@ -260,8 +268,8 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       if (step >= pl.npass) return 0;
       int b = pl.bits[step];
       int r2 = b > 4 ? (1 << (b - 4)) : 1;
-      // elements per workgroup: 256 / r2, twice that for complex64 radix 256
-      int e = (256 / r2) * ((mixed && b == 8) ? 2 : 1);
+      // elements per workgroup: 256 / r2, twice that with two rows per thread
+      int e = (256 / r2) * (qft_two_rows(mixed, b, n, t) ? 2 : 1);
       return cdiv((N * d) >> b, e);
     }
     case BK_PROB: {
@@ -427,9 +435,11 @@ hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* 
                                  hipStream_t s);
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                                    int bflags, hipStream_t s);
+// stage: some instance of the launch has d = 8 or 16 (rows staged in LDS).
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                                   int bflags, hipStream_t s);
+                                   bool stage, int bflags, hipStream_t s);
+// wide: some instance of the launch takes two rows per thread in this pass.
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
-                            int bflags, hipStream_t s);
+                            bool wide, int bflags, hipStream_t s);
 
 }  // namespace qpe
