@@ -188,6 +188,7 @@ def test_config2_full_size(qpe, form):
     say("c2", form, "max|dP| vs Fejer", err, "defect", rep["unitarity_defect"])
     assert err < (1e-6 if form == "mixed" else 1e-9)
     assert rep["flags"] == 0
+    assert abs(float(rep["prob_sum"]) - P.sum()) < 1e-12
 
 
 @pytest.mark.parametrize("form", ["mixed", "fp64"])
@@ -201,6 +202,25 @@ def test_config3_full_size(qpe, form):
     say("c3", form, "max|dP| vs closed form", err)
     assert err < (1e-6 if form == "mixed" else 1e-9)
     assert rep["flags"] == 0
+    assert abs(float(rep["prob_sum"]) - P.sum()) < 1e-12
+
+
+@pytest.mark.parametrize("n", [13, 14, 15])
+def test_report_sums(qpe, n):
+    """The per-run report on both sides of the two-stage probability sum
+    (2^14 outcomes and up): prob_sum against the host sum of the same P, and
+    ||psi||^2 for an input that is not normalised."""
+    say("report sums n", n)
+    rng = np.random.default_rng(900 + n)
+    U = haar_unitary(4, rng)
+    psi = (rng.standard_normal(4) + 1j * rng.standard_normal(4)) * 0.8
+    P, rep = qpe.run(dev(U), dev(psi), n, "mixed", report=True)
+    P = host(P)
+    norm2 = float(np.vdot(psi, psi).real)
+    assert rep["flags"] == 0
+    assert abs(float(rep["prob_sum"]) - P.sum()) < 1e-13 * n
+    assert abs(float(rep["psi_norm2"]) - norm2) < 1e-13
+    assert abs(P.sum() - norm2) < 1e-5
 
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
