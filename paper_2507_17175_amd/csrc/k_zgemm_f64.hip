@@ -454,8 +454,8 @@ hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int
 
 // Controlled step variants: 1: 64x64, 4 waves; 2: 128x64, 8 waves (the
 // default: with three accumulator sets per tile the 4-wave variant needs 280
-// VGPRs and runs one wave per SIMD: 3.4 ms vs 4.8 ms per c2 step). Small
-// sizes fall back to 32x32 tiles.
+// VGPRs and runs one wave per SIMD: 3.4 ms vs 4.8 ms per step at n = 16,
+// t = 10). Small sizes fall back to 32x32 tiles.
 hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n, int t, int k, uint64_t pmask,
                            hipStream_t s, int variant) {
   const int d = 1 << t;
