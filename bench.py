@@ -34,7 +34,10 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the controlled-product kernel at the c2 workload,
+# "dtype" is the matrix-core type of the dominant kernel; the whole path:
+DTYPE_DETAIL = "split-BF16 x6 products (FP32 accumulate) for the state GEMMs, FP32 QFT, FP64 powers and readout"
+
+# HBM bytes per launch of the controlled-product kernel at n = 16, t = 10,
 # from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors a plain 1 GiB copy gives), keyed by the first 16 hex digits of the
 # SHA-256 of the kernel source the counters were taken on. A changed kernel
@@ -121,7 +124,7 @@ def bench_batch(a, qpe, torch, config_problems):
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * el_g / a.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
+        "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitaries, eigenvector inputs)",
         "config": {"workload": CONFIGS[a.config], "instances": count, "form": "mixed", "graph": True},
         "autotune": tuned,
@@ -168,7 +171,7 @@ def bench_c5(a, qpe, torch):
         "metric": "QPE circuits/s (mixed form)",
         "value": round(steps / el, 5), "unit": "circuits/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * el / steps, 1), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
+        "vs_baseline": None, "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitary generated on the device, eigenvector input)",
         "config": {"workload": CONFIGS["c5"], "n_meas": n, "n_mat": t, "amplitudes": N * d, "form": "mixed",
                    "workspace_bytes": qpe.workspace_bytes([(n, t)], "mixed")},
@@ -449,7 +452,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x6->fp32 state GEMMs, fp32 QFT, fp64 powers/readout",
+        "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitary, eigenvector input)",
         "config": {"workload": CONFIGS[a.config], "n_meas": n, "n_mat": t, "amplitudes": N * d,
                    "state": "complex64", "U": "complex128", "form": "mixed"},
