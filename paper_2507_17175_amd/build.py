@@ -66,6 +66,26 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+CLIENT_SRC = os.path.join(ROOT, "tests", "c_client", "qpe_client.c")
+CLIENT = os.path.join(ROOT, "tests", "c_client", "qpe_client")
+
+
+def build_c_client(verbose: bool = False) -> str:
+    """The plain C caller of the ABI that the tests run (gcc, linked against
+    libqpe.so and the HIP runtime, found through an rpath)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    cmd = [shutil.which("gcc") or "cc", "-O2", "-std=c11", "-Wall", "-Wextra", "-I", INCLUDE,
+           "-I", os.path.join(rocm, "include"), "-D__HIP_PLATFORM_AMD__", CLIENT_SRC, "-o", CLIENT,
+           "-L", PKG, "-lqpe", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/../../paper_2507_17175_amd", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building the C client failed:\n{r.stdout}{r.stderr}")
+    return CLIENT
+
+
 def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 1)))
@@ -79,6 +99,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"linking libqpe.so failed:\n{r.stdout}{r.stderr}")
     os.replace(tmp, LIB)
+    build_c_client(verbose)
     return LIB
 
 
