@@ -74,7 +74,19 @@ enum {
    * [0, 2^k) times V_k^T. With this flag step k computes exactly those rows
    * from rows [0, 2^k): 2^n - 1 row products instead of n 2^(n-1), each row
    * receiving the same sequence of products as in the gate route. Same P. */
-  QPE_PREFIX_DOUBLING = 1u << 1
+  QPE_PREFIX_DOUBLING = 1u << 1,
+  /* Rotate the target register before the run: U <- M U M^T, psi <- M psi,
+   * with M = H D / sqrt(d) (H the Walsh-Hadamard matrix, D a fixed diagonal
+   * of signs; real orthogonal). P(m), a marginal over the target register,
+   * is unchanged in exact arithmetic. The mixed form's matrix-core products
+   * round each 16-term sum with an error of up to a few ulp; for an input
+   * spread over the d components those errors average out, for one
+   * concentrated on a few basis vectors they can add up over the n steps
+   * (a loss of total probability of ~1e-6 at N_meas = 16..20). M spreads
+   * such inputs. Costs two FP64 d x d products per run. Single instances
+   * (count = 1) with the polar step only; not with qpe_run_state.
+   * Otherwise: QPE_ERR_UNSUPPORTED. */
+  QPE_MIX_TARGET = 1u << 2
 };
 
 /* Report flags (qpe_report.flags). */

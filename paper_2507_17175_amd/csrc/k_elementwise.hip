@@ -337,6 +337,19 @@ __global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __res
              defect_bits);
 }
 
+// Rotation of the target register (see launch_mix_matrix): the sign of
+// column j of D is a fixed hash bit of j.
+__global__ void __launch_bounds__(kThreads) k_mix_matrix(double2* __restrict__ M, int t) {
+  const int64_t d = int64_t(1) << t, dd = d * d;
+  // 1 / sqrt(d): an exact power of two for even t
+  const double scale = ldexp(1.0, -(t / 2)) * ((t & 1) ? 0.70710678118654752440 : 1.0);
+  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+    const uint32_t i = uint32_t(e >> t), j = uint32_t(e & (d - 1));
+    const uint32_t neg = (__popc(i & j) + ((j * 2654435761u) >> 31)) & 1u;
+    M[e] = make_double2(neg ? -scale : scale, 0.0);
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0ull;
@@ -688,6 +701,12 @@ hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsi
   int64_t dd = int64_t(d) * d;
   hipLaunchKernelGGL(k_sub_identity_defect, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, G, G2, d,
                      defect_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix_matrix(double2* M, int t, hipStream_t s) {
+  const int64_t dd = int64_t(1) << (2 * t);
+  hipLaunchKernelGGL(k_mix_matrix, dim3(grid_for(dd)), dim3(kThreads), 0, s, M, t);
   return hipGetLastError();
 }
 

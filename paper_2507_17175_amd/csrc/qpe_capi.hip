@@ -159,7 +159,7 @@ qpe_status check_problem(const qpe_problem& p, bool need_ptrs) {
 
 qpe_status check_form_flags(int form, unsigned flags) {
   if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
-  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING)) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING | QPE_MIX_TARGET)) return QPE_ERR_ARG;
   return QPE_OK;
 }
 
@@ -331,13 +331,56 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
   const size_t amp = mixed ? 8 : 16;
   QPE_HIP(ctx, launch_zero_u64(defect, 1, s));
+  const double2* U0 = static_cast<const double2*>(p.U);
+  const double2* psi0 = psi;
+  if ((flags & QPE_MIX_TARGET) && polar) {
+    // Target rotation U' = M U M^T, psi' = M psi (P is unchanged). Buffers
+    // free at this point: M in the Gram buffer (first written by the power
+    // step of k = 1), U M^T in B (first written there as the square), U' in
+    // A (read as V_0 by step 0 and the first square, then overwritten by the
+    // polar step), M psi in the second state buffer (read by the H layer
+    // before step 0 writes there).
+    double2* Mx = G;
+    double2* T = B;
+    double2* Ur = A;
+    double2* pr = static_cast<double2*>(s1);
+    TimerScope ts(ctx, QPE_TIMER_POWERS);
+    QPE_HIP(ctx, launch_mix_matrix(Mx, t, s));
+    ZgemmArgs a{};
+    a.M = a.N = a.K = d;
+    a.lda = a.ldb = a.ldc = d;
+    a.alpha = make_double2(1.0, 0.0);
+    a.beta = make_double2(0.0, 0.0);
+    a.A = U0;
+    a.B = Mx;
+    a.C = T;
+    QPE_HIP(ctx, launch_zgemm(0, 1, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // U M^T
+    a.A = Mx;
+    a.B = T;
+    a.C = Ur;
+    QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M (U M^T)
+    ZgemmArgs v{};
+    v.M = d;
+    v.N = 1;
+    v.K = d;
+    v.lda = d;
+    v.ldb = v.ldc = 1;
+    v.alpha = make_double2(1.0, 0.0);
+    v.beta = make_double2(0.0, 0.0);
+    v.A = Mx;
+    v.B = psi;
+    v.C = pr;
+    QPE_HIP(ctx, launch_zgemm(0, 0, v, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M psi
+    U0 = Ur;
+    psi0 = pr;
+  }
   {
     // Prefix doubling writes every row j >= 1 in the step of its top bit,
     // so the H layer only has to fill row 0.
     TimerScope ts(ctx, QPE_TIMER_HLAYER);
-    QPE_HIP(ctx, launch_h_broadcast(mixed, psi, s0, n, t, s, dbl));
+    QPE_HIP(ctx, launch_h_broadcast(mixed, psi0, s0, n, t, s, dbl));
   }
-  const double2* cur = static_cast<const double2*>(p.U);
+  const double2* cur = U0;
   for (int k = 0; k < n; ++k) {
     bool planes_ready = false;  // the Newton-Schulz update already split V_k
     if (k > 0) {
@@ -765,6 +808,8 @@ QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int for
     if (s != QPE_OK) return s;
   }
   if (report && misaligned(report, 8)) return QPE_ERR_ALIGN;
+  // the target rotation runs in buffers of a single run that the polar step provides
+  if ((flags & QPE_MIX_TARGET) && (count > 1 || (flags & QPE_NO_POLAR))) return QPE_ERR_UNSUPPORTED;
   if (count > 1 && !plan_batch(problems, count, form, flags, true).ok) return QPE_ERR_SIZE;
   return check_workspace(workspace, workspace_bytes, workspace_need(problems, count, form, flags));
 }
@@ -784,6 +829,7 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
 QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags,
                                  void* workspace, size_t workspace_bytes, void* state_out, qpe_report* report) {
   if (!ctx || !state_out) return QPE_ERR_ARG;
+  if (flags & QPE_MIX_TARGET) return QPE_ERR_UNSUPPORTED;  // the state would be in the rotated basis
   qpe_status s = qpe_check_run(problem, 1, form, flags, workspace, workspace_bytes, report);
   if (s != QPE_OK) return s;
   if (misaligned(state_out, form == QPE_FORM_MIXED ? 8 : 16)) return QPE_ERR_ALIGN;

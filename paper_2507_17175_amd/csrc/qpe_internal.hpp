@@ -344,6 +344,9 @@ hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* o
 hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
                                       hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
+// M = H D / sqrt(d) (d x d complex128, imaginary parts 0): H the
+// Walsh-Hadamard matrix (-1)^popcount(i & j), D a fixed diagonal of signs.
+hipError_t launch_mix_matrix(double2* M, int t, hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
                        hipStream_t s);
 // part (optional): device scratch of 2^n / 256 bytes (16-byte aligned) for

@@ -24,6 +24,7 @@ FORM_MIXED = 1
 FORMS = {"fp64": FORM_FP64, "mixed": FORM_MIXED}
 NO_POLAR = 1
 PREFIX_DOUBLING = 2
+MIX_TARGET = 4
 REPORT_NOT_UNITARY = 1
 REPORT_NUMERIC = 2
 

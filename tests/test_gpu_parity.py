@@ -252,3 +252,53 @@ def test_batch_matches_single(qpe):
         Pb = host(P)
         assert np.array_equal(Pb, single)
         assert np.abs(Pb - O.fejer(p.phis[0], p.n_meas)).max() < 1e-6
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,t,seed", [(9, 5, 1), (7, 3, 2), (10, 7, 3), (6, 0, 4), (8, 10, 5)])
+def test_mix_target_keeps_P(qpe, form, n, t, seed):
+    """The target rotation (QPE_MIX_TARGET: U <- M U M^T, psi <- M psi with
+    M orthogonal) leaves P, a marginal over the target register, unchanged:
+    against the oracle's gate route for a general input."""
+    say("mix target", form, "n", n, "t", t)
+    rng = np.random.default_rng(1200 + seed)
+    d = 1 << t
+    U = haar_unitary(d, rng)
+    psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    psi /= np.linalg.norm(psi)
+    P = host(qpe.run(dev(U), dev(psi), n, form, flags=qpe.MIX_TARGET))
+    want = O.qpe_probs(U, psi, n)
+    assert np.abs(P - want).max() < (1e-6 if form == "mixed" else 1e-12)
+
+
+def _concentrated_case(n, t):
+    """An eigenvector that is almost e_0: U = Q diag(exp(2 pi i phi)) Q with Q
+    a Householder reflection, phi_0 = k / 2^n (exact bit), input Q e_0."""
+    d, N = 1 << t, 1 << n
+    i = np.arange(d)
+    v = 1.0 + 0.37 * i - 0.011 * i * i
+    Q = np.eye(d) - 2.0 * np.outer(v, v) / (v @ v)
+    k = 357 % N
+    phis = np.mod(0.1234567 + 0.7071067811865476 * i, 1.0)
+    phis[0] = k / N
+    return (Q * np.exp(2j * np.pi * phis)) @ Q, Q[:, 0].astype(np.complex128), k
+
+
+@pytest.mark.parametrize("n,t", [(16, 6), (20, 6)])
+def test_mix_target_concentrated_eigenvector(qpe, n, t):
+    """With the target rotation the mixed form keeps the 1e-6 target on an
+    almost-basis-vector eigenvector (all probability on m = k), where the
+    unrotated run loses ~1e-6 of total probability at these n."""
+    U, psi, k = _concentrated_case(n, t)
+    P = host(qpe.run(dev(U), dev(psi), n, "mixed", flags=qpe.MIX_TARGET))
+    want = np.zeros_like(P)
+    want[k] = 1.0
+    err = float(np.abs(P - want).max())
+    say("concentrated eigenvector, rotated, n", n, "t", t, "max|dP|", err)
+    assert err < 1e-6
+
+
+def test_mix_target_not_with_state_output(qpe):
+    U, psi, k = _concentrated_case(8, 3)
+    with pytest.raises(qpe.QpeError):
+        qpe.run_state(dev(U), dev(psi), 8, "mixed", flags=qpe.MIX_TARGET)
