@@ -83,9 +83,10 @@ enum {
    * spread over the d components those errors average out, for one
    * concentrated on a few basis vectors they can add up over the n steps
    * (a loss of total probability of ~1e-6 at N_meas = 16..20). M spreads
-   * such inputs. Costs two FP64 d x d products per run. Single instances
-   * (count = 1) with the polar step only; not with qpe_run_state.
-   * Otherwise: QPE_ERR_UNSUPPORTED. */
+   * such inputs. Costs two FP64 d x d products per instance. With the
+   * polar step only, and not with qpe_run_state (its state would be in the
+   * rotated basis): QPE_ERR_UNSUPPORTED there. Batched runs rotate every
+   * instance and give the same P as single runs, bit for bit. */
   QPE_MIX_TARGET = 1u << 2
 };
 

@@ -312,6 +312,42 @@ qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, cons
   return QPE_OK;
 }
 
+// Target rotation (QPE_MIX_TARGET): Ur = M U M^T and pr = M psi with
+// M = H D / sqrt(d) written to Mx, U M^T staged in T. P(m) is unchanged.
+qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* psi, double2* Mx, double2* T,
+                         double2* Ur, double2* pr) {
+  hipStream_t s = ctx->stream;
+  const int d = 1 << t;
+  TimerScope ts(ctx, QPE_TIMER_POWERS);
+  QPE_HIP(ctx, launch_mix_matrix(Mx, t, s));
+  ZgemmArgs a{};
+  a.M = a.N = a.K = d;
+  a.lda = a.ldb = a.ldc = d;
+  a.alpha = make_double2(1.0, 0.0);
+  a.beta = make_double2(0.0, 0.0);
+  a.A = U;
+  a.B = Mx;
+  a.C = T;
+  QPE_HIP(ctx, launch_zgemm(0, 1, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // U M^T
+  a.A = Mx;
+  a.B = T;
+  a.C = Ur;
+  QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M (U M^T)
+  ZgemmArgs v{};
+  v.M = d;
+  v.N = 1;
+  v.K = d;
+  v.lda = d;
+  v.ldb = v.ldc = 1;
+  v.alpha = make_double2(1.0, 0.0);
+  v.beta = make_double2(0.0, 0.0);
+  v.A = Mx;
+  v.B = psi;
+  v.C = pr;
+  QPE_HIP(ctx, launch_zgemm(0, 0, v, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M psi
+  return QPE_OK;
+}
+
 qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags, char* ws, qpe_report* report) {
   const int n = p.n_meas, t = p.n_mat, d = 1 << t;
   const bool mixed = form == QPE_FORM_MIXED;
@@ -334,43 +370,15 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   const double2* U0 = static_cast<const double2*>(p.U);
   const double2* psi0 = psi;
   if ((flags & QPE_MIX_TARGET) && polar) {
-    // Target rotation U' = M U M^T, psi' = M psi (P is unchanged). Buffers
-    // free at this point: M in the Gram buffer (first written by the power
-    // step of k = 1), U M^T in B (first written there as the square), U' in
-    // A (read as V_0 by step 0 and the first square, then overwritten by the
-    // polar step), M psi in the second state buffer (read by the H layer
-    // before step 0 writes there).
-    double2* Mx = G;
-    double2* T = B;
+    // Buffers free at this point: M in the Gram buffer (first written by the
+    // power step of k = 1), U M^T in B (first written there as the square),
+    // U' in A (read as V_0 by step 0 and the first square, then overwritten
+    // by the polar step), M psi in the second state buffer (read by the H
+    // layer before step 0 writes there).
     double2* Ur = A;
     double2* pr = static_cast<double2*>(s1);
-    TimerScope ts(ctx, QPE_TIMER_POWERS);
-    QPE_HIP(ctx, launch_mix_matrix(Mx, t, s));
-    ZgemmArgs a{};
-    a.M = a.N = a.K = d;
-    a.lda = a.ldb = a.ldc = d;
-    a.alpha = make_double2(1.0, 0.0);
-    a.beta = make_double2(0.0, 0.0);
-    a.A = U0;
-    a.B = Mx;
-    a.C = T;
-    QPE_HIP(ctx, launch_zgemm(0, 1, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // U M^T
-    a.A = Mx;
-    a.B = T;
-    a.C = Ur;
-    QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M (U M^T)
-    ZgemmArgs v{};
-    v.M = d;
-    v.N = 1;
-    v.K = d;
-    v.lda = d;
-    v.ldb = v.ldc = 1;
-    v.alpha = make_double2(1.0, 0.0);
-    v.beta = make_double2(0.0, 0.0);
-    v.A = Mx;
-    v.B = psi;
-    v.C = pr;
-    QPE_HIP(ctx, launch_zgemm(0, 0, v, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M psi
+    qpe_status st = rotate_target(ctx, t, U0, psi, G, B, Ur, pr);
+    if (st != QPE_OK) return st;
     U0 = Ur;
     psi0 = pr;
   }
@@ -452,8 +460,26 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
     int c = count - first < kBatchChunk ? count - first : kBatchChunk;
     for (int i = 0; i < c; ++i) {
       const qpe_problem& q = p[first + i];
-      chunk[i] = BatchProblem{q.n_meas, q.n_mat, q.U, q.psi, q.prob, report ? static_cast<void*>(report + first + i)
-                                                                            : nullptr,
+      const void* Uq = q.U;
+      const void* pq = q.psi;
+      if (flags & QPE_MIX_TARGET) {
+        // The instance's own idle buffers: the grouped power chain writes
+        // its first square to vbuf and its corrected power to tbuf, so U'
+        // sits in tbuf (read as V_0 by step 0 and by that square) and U M^T
+        // in vbuf; M in the Gram buffer, M psi in the second state buffer.
+        char* b = ws + P.inst_base[first + i];
+        const RunLayout L = run_layout(q.n_meas, q.n_mat, form, flags);
+        double2* Ur = reinterpret_cast<double2*>(b + L.tbuf);
+        double2* pr = reinterpret_cast<double2*>(b + L.state1);
+        qpe_status st = rotate_target(ctx, q.n_mat, static_cast<const double2*>(q.U),
+                                      static_cast<const double2*>(q.psi), reinterpret_cast<double2*>(b + L.gbuf),
+                                      reinterpret_cast<double2*>(b + L.vbuf), Ur, pr);
+        if (st != QPE_OK) return st;
+        Uq = Ur;
+        pq = pr;
+      }
+      chunk[i] = BatchProblem{q.n_meas, q.n_mat, Uq, pq, q.prob, report ? static_cast<void*>(report + first + i)
+                                                                          : nullptr,
                               uint64_t(P.inst_base[first + i])};
     }
     QPE_HIP(ctx, launch_batch_descs(desc, ws, chunk, first, c, s));
@@ -808,8 +834,8 @@ QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int for
     if (s != QPE_OK) return s;
   }
   if (report && misaligned(report, 8)) return QPE_ERR_ALIGN;
-  // the target rotation runs in buffers of a single run that the polar step provides
-  if ((flags & QPE_MIX_TARGET) && (count > 1 || (flags & QPE_NO_POLAR))) return QPE_ERR_UNSUPPORTED;
+  // the target rotation runs in buffers that the polar step provides
+  if ((flags & QPE_MIX_TARGET) && (flags & QPE_NO_POLAR)) return QPE_ERR_UNSUPPORTED;
   if (count > 1 && !plan_batch(problems, count, form, flags, true).ok) return QPE_ERR_SIZE;
   return check_workspace(workspace, workspace_bytes, workspace_need(problems, count, form, flags));
 }

@@ -93,13 +93,14 @@ def test_check_run(L):
     assert L.qpe_check_run(p, 1, 1, 0, ws + 16, need, None) == 4
     assert L.qpe_check_run(p, 1, 1, 0, None, need, None) == 4
     assert L.qpe_check_run(p, 1, 1, 0, ws, need, ws + 4) == 3
-    # the target rotation (flag 4): single instances with the polar step only
+    # the target rotation (flag 4): with the polar step only
     assert L.qpe_check_run(p, 1, 1, 4, ws, need, None) == 0
     assert L.qpe_check_run(p, 1, 1, 4 | 1, ws, need, None) == 8
     assert L.qpe_check_run(p, 1, 1, 8, ws, need, None) == 1
     two = _problems([(8, 2), (8, 2)])
     assert L.qpe_workspace_size(two, 2, 1, 0, ctypes.byref(out)) == 0
-    assert L.qpe_check_run(two, 2, 1, 4, ws, out.value, None) == 8
+    assert L.qpe_check_run(two, 2, 1, 4, ws, out.value, None) == 0
+    assert L.qpe_check_run(two, 2, 1, 4 | 1, ws, out.value, None) == 8
     bad = _problems([(8, 2)])
     bad[0].U = 0x10008
     assert L.qpe_check_run(bad, 1, 1, 0, ws, need, None) == 3

@@ -145,3 +145,28 @@ def test_batch_beyond_4096_instances(qpe, form):
     for i in range(0, len(probs), 499):
         U, psi, n = items[i]
         assert np.array_equal(host(qpe.run(U, psi, n, form=form)), host(out[i])), i
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_mix_target_matches_single(qpe, form):
+    """The target rotation in a batched run: every instance rotated in its
+    own buffers, the same P as the single flagged run, bit for bit, and the
+    oracle's P."""
+    say("batch mix target", form)
+    rng = np.random.default_rng(950)
+    shapes = [(9, 5), (7, 3), (10, 7), (6, 0), (8, 6), (11, 2)]
+    probs = []
+    for n, t in shapes:
+        d = 1 << t
+        U = haar_unitary(d, rng)
+        psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        psi /= np.linalg.norm(psi)
+        probs.append((U, psi, n))
+    dev_probs = [(dev(U), dev(psi), n) for U, psi, n in probs]
+    batch = qpe.run_batch(dev_probs, form, flags=qpe.MIX_TARGET)
+    tol = 1e-6 if form == "mixed" else 1e-12
+    for (U, psi, n), (Ud, pd, _), Pb in zip(probs, dev_probs, batch):
+        Pb = host(Pb)
+        single = host(qpe.run(Ud, pd, n, form, flags=qpe.MIX_TARGET))
+        assert np.array_equal(Pb, single), (n, U.shape[0])
+        assert np.abs(Pb - O.qpe_probs(U, psi, n)).max() < tol, (n, U.shape[0])
