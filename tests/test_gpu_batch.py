@@ -90,12 +90,12 @@ def test_config4_full_batch(qpe):
     assert np.all(rep["flags"] == 0)
 
 
-@pytest.mark.parametrize("form", ["mixed", "fp64"])
-def test_graph_replay_matches_eager(qpe, form):
+@pytest.mark.parametrize("form,flags", [("mixed", 0), ("fp64", 0), ("mixed", 4)])
+def test_graph_replay_matches_eager(qpe, form, flags):
     probs = config_problems("c4", count=24)
-    say("graph capture of a 24-instance batch", form)
+    say("graph capture of a 24-instance batch", form, flags)
     items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
-    runner = qpe.Runner(items, form=form)
+    runner = qpe.Runner(items, form=form, flags=flags)
     eager = [host(P).copy() for P in runner()]
     graph = qpe.CapturedRun(runner)
     for rep in range(3):
@@ -108,10 +108,10 @@ def test_graph_replay_matches_eager(qpe, form):
             assert np.array_equal(host(P), e), rep
 
 
-@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("flags", [0, 2, 4])
 def test_graph_replay_single_instance(qpe, flags):
-    # one instance (the single-run path, gate route and prefix doubling),
-    # captured: every replay must equal the eager run
+    # one instance (the single-run path: gate route, prefix doubling, and the
+    # target rotation), captured: every replay must equal the eager run
     p = make_problem(11, 7, np.random.default_rng(77))
     say("graph capture of one mixed instance", flags)
     items = [(dev(p.U), dev(p.psi), p.n_meas)]
