@@ -71,9 +71,12 @@ __device__ __forceinline__ void dft_regs(R* re, R* im) {
           re[st + i + s] = di;
           im[st + i + s] = -dr;
         } else {
-          const R c = R(c16(kw)), sn = R(s16(kw));
-          re[st + i + s] = dr * c + di * sn;
-          im[st + i + s] = di * c - dr * sn;
+          // rotated in FP64 with FP64 constants and rounded once: FP32
+          // constants miss c^2 + s^2 = 1 by 1e-8 to 6e-8, the same way for
+          // every element through this butterfly
+          const double c = c16(kw), sn = s16(kw), xr = double(dr), xi = double(di);
+          re[st + i + s] = R(xr * c + xi * sn);
+          im[st + i + s] = R(xi * c - xr * sn);
         }
       }
     }
