@@ -43,7 +43,7 @@ DTYPE_DETAIL = "split-BF16 x6 products (FP32 accumulate) for the state GEMMs, FP
 # SHA-256 of the kernel source the counters were taken on. A changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    "6c4a1f173bcc5eca": {"fetch_bytes": 524382.1 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
+    "6c4a1f173bcc5eca": {"fetch_bytes": 524376.0 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
                          "profile": "profiles/ctrl_bf16x6_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
