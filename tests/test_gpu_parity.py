@@ -133,6 +133,26 @@ def test_iqft_probs(qpe, form, n, t):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("n,t,k0", [(16, 6, 357), (16, 6, 65535), (18, 4, 12345), (20, 2, 699050)])
+def test_iqft_tone_keeps_norm(qpe, n, t, k0):
+    """Mixed form on a pure tone: the inverse DFT of exp(2 pi i j k0 / N)
+    is the basis vector k0 (Sec. 2, the inverse QFT), so all of the input's
+    norm must land on outcome k0. The rotations inside the register DFTs are
+    done in FP64; with FP32 roots of unity the norm drifted by about 1e-7 at
+    n = 16, the same way on every element."""
+    say("iqft tone", "n", n, "t", t, "k0", k0)
+    rng = np.random.default_rng(310 + n + t)
+    N, d = 1 << n, 1 << t
+    psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    psi /= np.linalg.norm(psi)
+    tone = np.exp(2j * np.pi * (np.arange(N) * k0 % N) / N) / math.sqrt(N)
+    S = (tone[:, None] * psi[None, :]).astype(np.complex64)
+    norm_in = float((np.abs(S.astype(np.complex128)) ** 2).sum())
+    P = host(qpe.iqft_probs(dev(S, torch.complex64), "mixed"))
+    assert abs(P.sum() - norm_in) < 6e-8, P.sum() - norm_in
+    assert abs(P[k0] - norm_in) < 6e-8, P[k0] - norm_in
+
+
 # ----------------------------------------------------------------- full runs
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
