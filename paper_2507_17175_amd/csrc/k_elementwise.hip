@@ -678,7 +678,7 @@ hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStre
 hipError_t launch_ns_prep_fused(const double2* X, const double2* G, const double2* G2, float2* X32, uint16_t* planes,
                                 int t, unsigned long long* defect_bits, hipStream_t s) {
   int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_ns_prep_fused, dim3(grid_for(dd, kThreads, 1024)), dim3(kThreads), 0, s, X, G, G2, X32, planes,
+  hipLaunchKernelGGL(k_ns_prep_fused, dim3(grid_for(dd, kThreads, 512)), dim3(kThreads), 0, s, X, G, G2, X32, planes,
                      t, defect_bits);
   return hipGetLastError();
 }
