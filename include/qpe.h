@@ -58,7 +58,8 @@ typedef enum qpe_status {
  *  QPE_FORM_MIXED: complex64 state; the controlled products run as split
  *                  BF16 matrix-core products (three BF16 pieces of each
  *                  operand, six partial products) accumulated in FP32; the
- *                  inverse QFT runs in FP32 and the readout sums in FP64.
+ *                  inverse QFT runs in FP32 and the readout sums in FP64;
+ *                  the target register is rotated first (QPE_MIX_TARGET).
  * In both forms the powers U^(2^k) are formed in FP64. */
 typedef enum qpe_form { QPE_FORM_FP64 = 0, QPE_FORM_MIXED = 1 } qpe_form;
 
@@ -75,25 +76,34 @@ enum {
    * from rows [0, 2^k): 2^n - 1 row products instead of n 2^(n-1), each row
    * receiving the same sequence of products as in the gate route. Same P. */
   QPE_PREFIX_DOUBLING = 1u << 1,
-  /* Rotate the target register before the run: U <- M U M^T, psi <- M psi,
-   * with M = H D / sqrt(d) (H the Walsh-Hadamard matrix, D a fixed diagonal
-   * of signs; real orthogonal). P(m), a marginal over the target register,
-   * is unchanged in exact arithmetic. The mixed form's matrix-core products
-   * round each 16-term sum with an error of up to a few ulp; for an input
-   * spread over the d components those errors average out, for one
-   * concentrated on a few basis vectors they can add up over the n steps
-   * (a loss of total probability of ~1e-6 at N_meas = 16..20). M spreads
-   * such inputs. Costs two FP64 d x d products per instance. With the
-   * polar step only, and not with qpe_run_state (its state would be in the
-   * rotated basis): QPE_ERR_UNSUPPORTED there. Batched runs rotate every
-   * instance and give the same P as single runs, bit for bit. */
-  QPE_MIX_TARGET = 1u << 2
+  /* Target rotation (on by default in QPE_FORM_MIXED for n_mat >= 5).
+   * Before the run U <- M U M^T and psi <- M psi with M = H D / sqrt(d): H the
+   * Walsh-Hadamard matrix, D a diagonal of signs derived from a hash of the
+   * bits of U and psi (of four candidate diagonals, the one that leaves the
+   * smallest peak weight max_i |(M psi)_i|^2 / ||psi||^2). M is real
+   * orthogonal, so P(m), a marginal over the target register (section 2,
+   * Fig. 1), is unchanged in exact arithmetic. Why: the mixed form's
+   * matrix-core products round each 16-term sum with an error of up to a
+   * few ulp; for state rows spread over the d components these errors
+   * average out, for rows concentrated on a few basis vectors (e.g. an
+   * eigenvector close to a basis vector) they add up coherently over the n
+   * steps (a loss of total probability of 1.5e-6 to 3.6e-6 at N_meas = 16
+   * to 20 without it). M spreads such inputs. Cost: a few Walsh-Hadamard
+   * passes over U (FP64, no d x d products). qpe_run_state rotates the final
+   * statevector back. QPE_MIX_TARGET forces the rotation on (any form, any
+   * n_mat >= 1); QPE_NO_MIX_TARGET turns it off; both: QPE_ERR_ARG. */
+  QPE_MIX_TARGET = 1u << 2,
+  QPE_NO_MIX_TARGET = 1u << 3
 };
 
 /* Report flags (qpe_report.flags). */
 enum {
   QPE_REPORT_NOT_UNITARY = 1u << 0, /* max|V^H V - I| above 1e-6 at some step */
-  QPE_REPORT_NUMERIC = 1u << 1      /* NaN/Inf in P, or |sum P - |psi|^2| > 1e-4*|psi|^2 */
+  QPE_REPORT_NUMERIC = 1u << 1,     /* NaN/Inf in P, or |sum P - |psi|^2| > 1e-4*|psi|^2 */
+  /* mixed form, n_mat >= 5: the input the matrix cores see (M psi when
+   * rotated, else psi) holds more than half of its norm on one basis vector
+   * (input_peak > 0.5), the case whose rounding errors add up coherently */
+  QPE_REPORT_CONCENTRATED = 1u << 2
 };
 
 /* Limits. d = 2^n_mat, N = 2^n_meas. */
@@ -115,11 +125,14 @@ typedef struct qpe_problem {
 /* Device-written diagnostics, one per instance (caller-owned device memory,
  * 8-byte aligned). unitarity_defect is the largest max-norm of V^H V - I met
  * before each Newton-Schulz step (0 when QPE_NO_POLAR); prob_sum = sum_m P(m);
- * psi_norm2 = ||psi||^2. */
+ * psi_norm2 = ||psi||^2; input_peak = max_i |x_i|^2 / ||psi||^2 for the input
+ * x of the state path (M psi when the target register was rotated, else
+ * psi). */
 typedef struct qpe_report {
   double unitarity_defect;
   double prob_sum;
   double psi_norm2;
+  double input_peak;
   uint32_t flags;
   uint32_t reserved;
 } qpe_report;
@@ -161,8 +174,9 @@ qpe_status qpe_run(qpe_ctx *ctx, const qpe_problem *problems, int count, int for
  * (section 3), whose norms give the outcome distribution. state_out
  * (device, caller-owned, N*d elements) receives A[m, r] of the formula at the
  * top of this header, row-major in natural outcome order m: complex64 for
- * QPE_FORM_MIXED, complex128 for QPE_FORM_FP64. prob and report are written
- * as by qpe_run. Same workspace as qpe_run for this one problem.
+ * QPE_FORM_MIXED, complex128 for QPE_FORM_FP64 (a run with the target
+ * rotation rotates it back). prob and report are written as by qpe_run.
+ * Same workspace as qpe_run for this one problem.
  * Errors: as qpe_run; QPE_ERR_ALIGN if state_out is not aligned to its
  * element size. */
 qpe_status qpe_run_state(qpe_ctx *ctx, const qpe_problem *problem, int form, unsigned flags,

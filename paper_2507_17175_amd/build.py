@@ -30,6 +30,7 @@ SOURCES = [
     "k_ctrl_small.hip",
     "k_qft.hip",
     "k_estimate.hip",
+    "k_rotate.hip",
 ]
 
 ARCH = "gfx950"

@@ -181,17 +181,21 @@ __device__ inline void prob_rows(const T* __restrict__ X, double* __restrict__ p
   if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
 }
 
-// Report: prob_sum, ||psi||^2, the defect and the flags, by one block. With
-// `part` (nparts pairs: partial sum, non-finite flag, from k_report_partial)
-// it adds the partial sums instead of reading the 2^n probabilities itself.
+// Report: prob_sum, ||psi||^2, the input's peak weight, the defect and the
+// flags, by one block. With `part` (nparts pairs: partial sum, non-finite
+// flag, from k_report_partial) it adds the partial sums instead of reading
+// the 2^n probabilities itself. rot_peak: the rotated input's peak weight, or
+// null for max_i |psi_i|^2 / ||psi||^2 of psi itself; check: flag a peak
+// weight above kPeakFlag.
 __device__ inline void report_block(const double* __restrict__ prob, int n, const double2* __restrict__ psi, int t,
-                                    const unsigned long long* __restrict__ defect_bits, double* __restrict__ report,
+                                    const unsigned long long* __restrict__ defect_bits,
+                                    const double* __restrict__ rot_peak, bool check, double* __restrict__ report,
                                     const double* __restrict__ part = nullptr, int nparts = 0) {
-  __shared__ double red[2][kThreads];
+  __shared__ double red[3][kThreads];
   __shared__ int any_bad;
   const int64_t N = int64_t(1) << n;
   const int d = 1 << t;
-  double s = 0.0, q = 0.0;
+  double s = 0.0, q = 0.0, mx = 0.0;
   bool bad = false;
   if (part) {
     for (int i = threadIdx.x; i < nparts; i += kThreads) {
@@ -205,9 +209,14 @@ __device__ inline void report_block(const double* __restrict__ prob, int n, cons
       s += v;
     }
   }
-  for (int i = threadIdx.x; i < d; i += kThreads) q += psi[i].x * psi[i].x + psi[i].y * psi[i].y;
+  for (int i = threadIdx.x; i < d; i += kThreads) {
+    const double w = psi[i].x * psi[i].x + psi[i].y * psi[i].y;
+    q += w;
+    mx = fmax(mx, w);
+  }
   red[0][threadIdx.x] = s;
   red[1][threadIdx.x] = q;
+  red[2][threadIdx.x] = mx;
   if (threadIdx.x == 0) any_bad = 0;
   __syncthreads();
   if (bad) atomicOr(&any_bad, 1);
@@ -215,20 +224,24 @@ __device__ inline void report_block(const double* __restrict__ prob, int n, cons
     if (int(threadIdx.x) < w) {
       red[0][threadIdx.x] += red[0][threadIdx.x + w];
       red[1][threadIdx.x] += red[1][threadIdx.x + w];
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + w]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     double defect = defect_bits ? __longlong_as_double((long long)defect_bits[0]) : 0.0;
     double ps = red[0][0], pn = red[1][0];
+    const double peak = rot_peak ? rot_peak[0] : (pn > 0.0 ? red[2][0] / pn : 0.0);
     unsigned flags = 0;
     if (defect > 1e-6 || defect != defect) flags |= 1u;
     if (any_bad || !(fabs(ps - pn) <= 1e-4 * pn)) flags |= 2u;
+    if (check && peak > kPeakFlag) flags |= 4u;
     report[0] = defect;
     report[1] = ps;
     report[2] = pn;
-    reinterpret_cast<uint32_t*>(report + 3)[0] = flags;
-    reinterpret_cast<uint32_t*>(report + 3)[1] = 0u;
+    report[3] = peak;
+    reinterpret_cast<uint32_t*>(report + 4)[0] = flags;
+    reinterpret_cast<uint32_t*>(report + 4)[1] = 0u;
   }
 }
 
@@ -337,19 +350,6 @@ __global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __res
              defect_bits);
 }
 
-// Rotation of the target register (see launch_mix_matrix): the sign of
-// column j of D is a fixed hash bit of j.
-__global__ void __launch_bounds__(kThreads) k_mix_matrix(double2* __restrict__ M, int t) {
-  const int64_t d = int64_t(1) << t, dd = d * d;
-  // 1 / sqrt(d): an exact power of two for even t
-  const double scale = ldexp(1.0, -(t / 2)) * ((t & 1) ? 0.70710678118654752440 : 1.0);
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
-    const uint32_t i = uint32_t(e >> t), j = uint32_t(e & (d - 1));
-    const uint32_t neg = (__popc(i & j) + ((j * 2654435761u) >> 31)) & 1u;
-    M[e] = make_double2(neg ? -scale : scale, 0.0);
-  }
-}
-
 __global__ void k_zero_u64(unsigned long long* p, int count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0ull;
@@ -400,9 +400,10 @@ __global__ void __launch_bounds__(kThreads) k_gather_state(const T* __restrict__
 __global__ void __launch_bounds__(kThreads) k_report(const double* __restrict__ prob, int n,
                                                      const double2* __restrict__ psi, int t,
                                                      const unsigned long long* __restrict__ defect_bits,
+                                                     const double* __restrict__ rot_peak, int check,
                                                      double* __restrict__ report, const double* __restrict__ part,
                                                      int nparts) {
-  report_block(prob, n, psi, t, defect_bits, report, part, nparts);
+  report_block(prob, n, psi, t, defect_bits, rot_peak, check != 0, report, part, nparts);
 }
 
 // First stage of the report for large registers: block b sums the
@@ -467,6 +468,8 @@ __global__ void k_batch_descs(InstDesc* __restrict__ desc, char* ws, DescArgs a)
   D.t = p.t;
   D.U = static_cast<const double2*>(p.U);
   D.psi = static_cast<const double2*>(p.psi);
+  D.U_src = static_cast<const double2*>(p.U_src);
+  D.psi_src = static_cast<const double2*>(p.psi_src);
   D.prob = p.prob;
   D.report = static_cast<double*>(p.report);
   D.ws = ws + p.ws_offset;
@@ -568,10 +571,17 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
     case BK_HLAYER: {
       // the prefix-doubling form only needs row 0
       int64_t e0 = local * kHTile, e1 = min(e0 + int64_t(kHTile), dbl ? int64_t(d) : N * d);
-      if (mixed)
+      if (mixed) {
         h_range_c64(D.psi, reinterpret_cast<float4*>(D.ws + L.state0), e0 / 2 + threadIdx.x, e1 / 2, d - 1,
                     h_scale(n), kThreads);
-      else
+        // an odd element count (row 0 alone with d = 1, prefix doubling) ends
+        // with one amplitude the pair writes do not cover
+        if ((e1 & 1) && threadIdx.x == 0) {
+          const double2 a = D.psi[(e1 - 1) & (d - 1)];
+          const double sc = h_scale(n);
+          reinterpret_cast<float2*>(D.ws + L.state0)[e1 - 1] = make_float2(float(a.x * sc), float(a.y * sc));
+        }
+      } else
         h_range_c128(D.psi, reinterpret_cast<double2*>(D.ws + L.state0), e0 + threadIdx.x, e1, d - 1, h_scale(n),
                      kThreads);
       break;
@@ -626,7 +636,12 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       break;
     }
     case BK_REPORT:
-      if (D.report) report_block(D.prob, n, D.psi, t, polar ? defect : nullptr, D.report);
+      if (D.report) {
+        const bool rot = rotate_on(mixed, t, batch_rot_mode(bflags));
+        report_block(D.prob, n, D.psi_src, t, polar ? defect : nullptr,
+                     rot ? reinterpret_cast<const double*>(defect + kScratchPeak) : nullptr, mixed && t >= 5,
+                     D.report);
+      }
       break;
   }
 }
@@ -704,12 +719,6 @@ hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsi
   return hipGetLastError();
 }
 
-hipError_t launch_mix_matrix(double2* M, int t, hipStream_t s) {
-  const int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_mix_matrix, dim3(grid_for(dd)), dim3(kThreads), 0, s, M, t);
-  return hipGetLastError();
-}
-
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
   return hipGetLastError();
@@ -733,15 +742,15 @@ hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t
 }
 
 hipError_t launch_report(const double* prob, int n, const double2* psi, int t, const unsigned long long* defect_bits,
-                         void* report, double* part, hipStream_t s) {
+                         const double* rot_peak, bool check, void* report, double* part, hipStream_t s) {
   const int64_t N = int64_t(1) << n;
   int nparts = 0;
   if (part && N >= 4 * kReportChunk) {
     nparts = int(N / kReportChunk);
     hipLaunchKernelGGL(k_report_partial, dim3(nparts), dim3(kThreads), 0, s, prob, part);
   }
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, s, prob, n, psi, t, defect_bits,
-                     static_cast<double*>(report), nparts ? part : nullptr, nparts);
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(kThreads), 0, s, prob, n, psi, t, defect_bits, rot_peak,
+                     check ? 1 : 0, static_cast<double*>(report), nparts ? part : nullptr, nparts);
   return hipGetLastError();
 }
 

@@ -51,6 +51,12 @@ RunLayout run_layout(int n, int t, int form, unsigned flags) {
   return qpe::run_layout(n, t, form == QPE_FORM_MIXED, !(flags & QPE_NO_POLAR));
 }
 
+int rot_mode(unsigned flags) {
+  if (flags & QPE_MIX_TARGET) return kRotForce;
+  if (flags & QPE_NO_MIX_TARGET) return kRotOff;
+  return kRotDefault;
+}
+
 // ---- batched runs -------------------------------------------------------
 //
 // Workspace of a batched run: [launch tables][instance descriptors]
@@ -70,6 +76,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
   BatchPlan P;
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
+  tile_flags |= rot_mode(flags) << kBatchRotShift;
   int32_t table_ints = 0;
   auto add = [&](int kind, int step) {
     int members = 0;
@@ -87,13 +94,20 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
     P.tiles.push_back(tiles);
     table_ints += 2 + 2 * members;
   };
-  int maxn = 0, maxpass = 0;
+  int maxn = 0, maxpass = 0, maxrot = 0;
   for (int i = 0; i < count; ++i) {
     maxn = p[i].n_meas > maxn ? p[i].n_meas : maxn;
     int np = make_dft_plan(p[i].n_meas).npass;
     maxpass = np > maxpass ? np : maxpass;
+    if (rotate_on(mixed, p[i].n_mat, rot_mode(flags))) {
+      np = rot_plan(p[i].n_mat).npass;
+      maxrot = np > maxrot ? np : maxrot;
+    }
   }
   add(BK_ZERO, 0);
+  add(BK_ROTHASH, 0);
+  add(BK_ROTPSI, 0);
+  for (int q = 0; q < maxrot; ++q) add(BK_ROTU, q);
   add(BK_HLAYER, 0);
   add(BK_TWIDDLE, 0);
   for (int k = 0; k < maxn; ++k) {
@@ -159,7 +173,8 @@ qpe_status check_problem(const qpe_problem& p, bool need_ptrs) {
 
 qpe_status check_form_flags(int form, unsigned flags) {
   if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
-  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING | QPE_MIX_TARGET)) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING | QPE_MIX_TARGET | QPE_NO_MIX_TARGET)) return QPE_ERR_ARG;
+  if ((flags & QPE_MIX_TARGET) && (flags & QPE_NO_MIX_TARGET)) return QPE_ERR_ARG;
   return QPE_OK;
 }
 
@@ -312,39 +327,15 @@ qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, cons
   return QPE_OK;
 }
 
-// Target rotation (QPE_MIX_TARGET): Ur = M U M^T and pr = M psi with
-// M = H D / sqrt(d) written to Mx, U M^T staged in T. P(m) is unchanged.
-qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* psi, double2* Mx, double2* T,
-                         double2* Ur, double2* pr) {
+// Target rotation: Ur = M U M^T and pr = M psi with M = H D / sqrt(d), the
+// key of D and the peak weight of pr in the instance's scratch words.
+qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* psi, double2* Ur, double2* pr,
+                         unsigned long long* scratch) {
   hipStream_t s = ctx->stream;
-  const int d = 1 << t;
   TimerScope ts(ctx, QPE_TIMER_POWERS);
-  QPE_HIP(ctx, launch_mix_matrix(Mx, t, s));
-  ZgemmArgs a{};
-  a.M = a.N = a.K = d;
-  a.lda = a.ldb = a.ldc = d;
-  a.alpha = make_double2(1.0, 0.0);
-  a.beta = make_double2(0.0, 0.0);
-  a.A = U;
-  a.B = Mx;
-  a.C = T;
-  QPE_HIP(ctx, launch_zgemm(0, 1, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // U M^T
-  a.A = Mx;
-  a.B = T;
-  a.C = Ur;
-  QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M (U M^T)
-  ZgemmArgs v{};
-  v.M = d;
-  v.N = 1;
-  v.K = d;
-  v.lda = d;
-  v.ldb = v.ldc = 1;
-  v.alpha = make_double2(1.0, 0.0);
-  v.beta = make_double2(0.0, 0.0);
-  v.A = Mx;
-  v.B = psi;
-  v.C = pr;
-  QPE_HIP(ctx, launch_zgemm(0, 0, v, s, ctx->variant[QPE_KERNEL_ZGEMM][t]));  // M psi
+  QPE_HIP(ctx, launch_rot_hash(U, t, scratch, s));
+  QPE_HIP(ctx, launch_rot_psi(psi, t, scratch, pr, s));
+  QPE_HIP(ctx, launch_rot_u(U, Ur, t, scratch, s));
   return QPE_OK;
 }
 
@@ -369,15 +360,15 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   QPE_HIP(ctx, launch_zero_u64(defect, 1, s));
   const double2* U0 = static_cast<const double2*>(p.U);
   const double2* psi0 = psi;
-  if ((flags & QPE_MIX_TARGET) && polar) {
-    // Buffers free at this point: M in the Gram buffer (first written by the
-    // power step of k = 1), U M^T in B (first written there as the square),
-    // U' in A (read as V_0 by step 0 and the first square, then overwritten
-    // by the polar step), M psi in the second state buffer (read by the H
-    // layer before step 0 writes there).
+  const bool rot = rotate_on(mixed, t, rot_mode(flags));
+  if (rot) {
+    // U' goes to A: it is read as V_0 by step 0 and by the first square,
+    // which writes B; A is next written by the power step of k = 1 (polar)
+    // or k = 2. M psi goes to the second state buffer, read by the H layer
+    // before step 0 writes there (the prefix-doubling form never does).
     double2* Ur = A;
     double2* pr = static_cast<double2*>(s1);
-    qpe_status st = rotate_target(ctx, t, U0, psi, G, B, Ur, pr);
+    qpe_status st = rotate_target(ctx, t, U0, psi, Ur, pr, defect);
     if (st != QPE_OK) return st;
     U0 = Ur;
     psi0 = pr;
@@ -415,7 +406,9 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   if (st != QPE_OK) return st;
   // the second state buffer is free once the inverse QFT has read it
   if (report)
-    QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr, report, static_cast<double*>(s1), s));
+    QPE_HIP(ctx, launch_report(p.prob, n, psi, t, polar ? defect : nullptr,
+                               rot ? reinterpret_cast<const double*>(defect + kScratchPeak) : nullptr,
+                               mixed && t >= 5, report, static_cast<double*>(s1), s));
   return QPE_OK;
 }
 
@@ -426,6 +419,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
 int timer_of(int kind) {
   switch (kind) {
     case BK_HLAYER: return QPE_TIMER_HLAYER;
+    case BK_ROTHASH: case BK_ROTPSI: case BK_ROTU: return QPE_TIMER_POWERS;
     case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR:
     case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD:
       return QPE_TIMER_POWERS;
@@ -450,7 +444,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
                      qpe_report* report) {
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0) |
-                 batch_variant_flags(ctx);
+                 batch_variant_flags(ctx) | (rot_mode(flags) << kBatchRotShift);
   hipStream_t s = ctx->stream;
   const BatchPlan P = plan_batch(p, count, form, flags, true, bf & kBatchGemm64);
   int32_t* tables = reinterpret_cast<int32_t*>(ws);
@@ -462,24 +456,19 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       const qpe_problem& q = p[first + i];
       const void* Uq = q.U;
       const void* pq = q.psi;
-      if (flags & QPE_MIX_TARGET) {
-        // The instance's own idle buffers: the grouped power chain writes
-        // its first square to vbuf and its corrected power to tbuf, so U'
-        // sits in tbuf (read as V_0 by step 0 and by that square) and U M^T
-        // in vbuf; M in the Gram buffer, M psi in the second state buffer.
+      if (rotate_on(mixed, q.n_mat, rot_mode(flags))) {
+        // The instance's own idle buffers: the grouped power chain writes its
+        // first square to vbuf and its corrected power (or, without the
+        // polar step, the square of k = 2) to tbuf, so U' sits in tbuf (read
+        // as V_0 by step 0 and by the first square); M psi in the second
+        // state buffer. The grouped rotation kernels write both.
         char* b = ws + P.inst_base[first + i];
         const RunLayout L = run_layout(q.n_meas, q.n_mat, form, flags);
-        double2* Ur = reinterpret_cast<double2*>(b + L.tbuf);
-        double2* pr = reinterpret_cast<double2*>(b + L.state1);
-        qpe_status st = rotate_target(ctx, q.n_mat, static_cast<const double2*>(q.U),
-                                      static_cast<const double2*>(q.psi), reinterpret_cast<double2*>(b + L.gbuf),
-                                      reinterpret_cast<double2*>(b + L.vbuf), Ur, pr);
-        if (st != QPE_OK) return st;
-        Uq = Ur;
-        pq = pr;
+        Uq = b + L.tbuf;
+        pq = b + L.state1;
       }
-      chunk[i] = BatchProblem{q.n_meas, q.n_mat, Uq, pq, q.prob, report ? static_cast<void*>(report + first + i)
-                                                                          : nullptr,
+      chunk[i] = BatchProblem{q.n_meas, q.n_mat, Uq, pq, q.U, q.psi, q.prob,
+                              report ? static_cast<void*>(report + first + i) : nullptr,
                               uint64_t(P.inst_base[first + i])};
     }
     QPE_HIP(ctx, launch_batch_descs(desc, ws, chunk, first, c, s));
@@ -515,6 +504,11 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
         break;
       case BK_CTRL_F64:
         QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, bf, s));
+        break;
+      case BK_ROTHASH:
+      case BK_ROTPSI:
+      case BK_ROTU:
+        QPE_HIP(ctx, launch_batch_rotate(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
         break;
       case BK_QFT: {
         bool wide = false;  // an instance takes two rows per thread in this pass
@@ -834,8 +828,6 @@ QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int for
     if (s != QPE_OK) return s;
   }
   if (report && misaligned(report, 8)) return QPE_ERR_ALIGN;
-  // the target rotation runs in buffers that the polar step provides
-  if ((flags & QPE_MIX_TARGET) && (flags & QPE_NO_POLAR)) return QPE_ERR_UNSUPPORTED;
   if (count > 1 && !plan_batch(problems, count, form, flags, true).ok) return QPE_ERR_SIZE;
   return check_workspace(workspace, workspace_bytes, workspace_need(problems, count, form, flags));
 }
@@ -855,7 +847,6 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
 QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags,
                                  void* workspace, size_t workspace_bytes, void* state_out, qpe_report* report) {
   if (!ctx || !state_out) return QPE_ERR_ARG;
-  if (flags & QPE_MIX_TARGET) return QPE_ERR_UNSUPPORTED;  // the state would be in the rotated basis
   qpe_status s = qpe_check_run(problem, 1, form, flags, workspace, workspace_bytes, report);
   if (s != QPE_OK) return s;
   if (misaligned(state_out, form == QPE_FORM_MIXED ? 8 : 16)) return QPE_ERR_ALIGN;
@@ -870,6 +861,12 @@ QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int f
   const double scale = std::ldexp(1.0, -(n / 2)) * ((n & 1) ? std::sqrt(0.5) : 1.0);
   QPE_HIP(ctx, launch_gather_state(form == QPE_FORM_MIXED, static_cast<char*>(workspace) + L.state0, state_out, n,
                                    t, make_dft_plan(n), scale, ctx->stream));
+  // a rotated run's final state is M times the circuit's: rotate it back
+  if (rotate_on(form == QPE_FORM_MIXED, t, rot_mode(flags)))
+    QPE_HIP(ctx, launch_unrotate_state(form == QPE_FORM_MIXED, state_out, n, t,
+                                       reinterpret_cast<const unsigned long long*>(static_cast<char*>(workspace) +
+                                                                                   L.scratch),
+                                       ctx->stream));
   return QPE_OK;
 }
 

@@ -102,6 +102,15 @@ __host__ __device__ inline int tw_split(int n) { return (n + 1) / 2; }
 // path splits at the same sizes, so both paths add the same partial sums.
 __host__ __device__ inline bool gram_split(int t) { return t == 10 || t == 11; }
 
+// The instance's small scratch region holds, as 8-byte words: the unitarity
+// defect (the bits of a non-negative double, atomically maxed), the key of the
+// target rotation, the rotated input's peak weight, and from word
+// kScratchHash on the partial hashes of the rotation key (kRotHashBlocks).
+constexpr int kScratchDefect = 0, kScratchKey = 1, kScratchPeak = 2, kScratchHash = 8;
+constexpr int kRotHashBlocks = 256;
+constexpr int kRotHashChunk = 4096;  // operator elements per hash chunk
+constexpr size_t kScratchBytes = (kScratchHash + kRotHashBlocks) * 8;
+
 // Regions of one instance's workspace (byte offsets from its base).
 struct RunLayout {
   size_t state0, state1, vbuf, tbuf, gbuf, gbuf2, planes, tw_hi, tw_lo, scratch, total;
@@ -133,9 +142,21 @@ __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool p
   L.tw_lo = off;
   off = align_up(off + (size_t(1) << h) * 16);
   L.scratch = off;
-  off = align_up(off + 64);
+  off = align_up(off + kScratchBytes);
   L.total = off;
   return L;
+}
+
+// Target rotation (paper section 2: P(m) is a marginal over the target
+// register, so an orthogonal change of that register's basis leaves it
+// unchanged): U <- M U M^T, psi <- M psi with M = H D / sqrt(d), H the
+// Walsh-Hadamard matrix and D a diagonal of signs drawn from a hash of U and
+// psi. It is on by default in the mixed form for d >= 32 (the matrix-core
+// path), forced on by QPE_MIX_TARGET and off with QPE_NO_MIX_TARGET.
+enum RotMode { kRotDefault = 0, kRotForce = 1, kRotOff = 2 };
+__host__ __device__ inline bool rotate_on(bool mixed, int t, int mode) {
+  if (t == 0 || mode == kRotOff) return false;
+  return mode == kRotForce || (mixed && t >= 5);
 }
 
 // Where V_k lives during a run: 0 = U itself, 1 = vbuf, 2 = tbuf. With the
@@ -157,6 +178,9 @@ __host__ __device__ inline int power_slot(int k, bool polar) {
 
 enum BatchKind {
   BK_ZERO = 0,
+  BK_ROTHASH,  // target rotation: partial hashes of U,
+  BK_ROTPSI,   //   the key, M psi and its peak weight,
+  BK_ROTU,     //   the Walsh-Hadamard passes of U (step = pass)
   BK_HLAYER,
   BK_TWIDDLE,
   BK_SQ,
@@ -180,6 +204,8 @@ enum BatchKind {
   BK_COUNT
 };
 
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 constexpr int kHTile = 4096;     // complex amplitudes per H-layer tile
 constexpr int kSplitTile = 4096; // operator elements per split tile
 constexpr int kSubiTile = 16384; // operator elements per identity-subtraction tile
@@ -188,14 +214,23 @@ constexpr int kProbRounds = 8;   // row groups per readout workgroup
 
 struct InstDesc {
   int32_t n, t;
-  const double2* U;
-  const double2* psi;
+  const double2* U;    // the operator the run uses (rotated, when rotated)
+  const double2* psi;  // the input the run uses (rotated, when rotated)
+  const double2* U_src;    // the caller's U and psi
+  const double2* psi_src;
   double* prob;
-  double* report;  // 4 doubles, or null
+  double* report;  // 5 doubles, or null
   char* ws;        // this instance's region of the workspace
 };
 
-__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// Passes of the Walsh-Hadamard transform over the 2t bits of a flattened
+// d x d operator (balanced passes of at most 8 bits, as the DFT plan).
+__host__ __device__ inline DftPlan rot_plan(int t) { return make_dft_plan(2 * t); }
+constexpr int kWhtTile = 2048;  // elements per Walsh-Hadamard tile
+__host__ __device__ inline int64_t rot_hash_blocks(int t) {
+  const int64_t c = cdiv(int64_t(1) << (2 * t), kRotHashChunk);
+  return c < kRotHashBlocks ? c : kRotHashBlocks;
+}
 
 // Workgroups instance (n, t) contributes to launch (kind, step); 0 if it
 // takes no part. step = controlled step k, or the DFT pass index.
@@ -205,6 +240,9 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // controlled step uses the in-step schedule instead of the ping-pong one.
 // Neither changes the order of any sum, so results are the same bit for bit.
 constexpr int kBatchPolar = 1, kBatchDoubling = 2, kBatchGemm64 = 4, kBatchCtrlInStep = 8;
+// target rotation mode (RotMode) in bits 4-5
+constexpr int kBatchRotShift = 4;
+__host__ __device__ inline int batch_rot_mode(int bflags) { return (bflags >> kBatchRotShift) & 3; }
 
 // Tile edge of the grouped power-chain products of an instance with 2^t x 2^t
 // operators.
@@ -221,6 +259,15 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
   switch (kind) {
     case BK_ZERO:
       return 1;
+    case BK_ROTHASH:
+      return rotate_on(mixed, t, batch_rot_mode(bflags)) ? rot_hash_blocks(t) : 0;
+    case BK_ROTPSI:
+      return rotate_on(mixed, t, batch_rot_mode(bflags)) ? 1 : 0;
+    case BK_ROTU: {
+      if (!rotate_on(mixed, t, batch_rot_mode(bflags))) return 0;
+      const DftPlan pl = rot_plan(t);
+      return step < pl.npass ? cdiv(d * d, kWhtTile) : 0;
+    }
     case BK_HLAYER:
       return cdiv(dbl ? d : N * d, kHTile);
     case BK_TWIDDLE: {
@@ -344,15 +391,31 @@ hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* o
 hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
                                       hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
-// M = H D / sqrt(d) (d x d complex128, imaginary parts 0): H the
-// Walsh-Hadamard matrix (-1)^popcount(i & j), D a fixed diagonal of signs.
-hipError_t launch_mix_matrix(double2* M, int t, hipStream_t s);
+// Target rotation (k_rotate.hip). scratch: the instance's scratch words
+// (kScratch*). launch_rot_hash writes the partial hashes of U;
+// launch_rot_psi combines them with a hash of psi into the key, tries four
+// sign diagonals derived from it and keeps the one whose M psi has the
+// smallest peak weight max_i |(M psi)_i|^2 / ||psi||^2 (key and peak into
+// scratch, M psi into psi_out); launch_rot_u writes Ur = M U M^T.
+hipError_t launch_rot_hash(const double2* U, int t, unsigned long long* scratch, hipStream_t s);
+hipError_t launch_rot_psi(const double2* psi, int t, unsigned long long* scratch, double2* psi_out, hipStream_t s);
+hipError_t launch_rot_u(const double2* U, double2* Ur, int t, const unsigned long long* scratch, hipStream_t s);
+// Undo the rotation on a final statevector (N x d, outcome rows): every row
+// a <- M^T a (complex64 when mixed, else complex128), in place.
+hipError_t launch_unrotate_state(bool mixed, void* state, int n, int t, const unsigned long long* scratch,
+                                 hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
                        hipStream_t s);
 // part (optional): device scratch of 2^n / 256 bytes (16-byte aligned) for
 // the partial sums of a two-stage sum when 2^n >= 16384.
+// rot_peak: the rotated input's peak weight (scratch word kScratchPeak) when
+// the run rotated, else null (the peak of psi itself is reported); check:
+// flag QPE_REPORT_CONCENTRATED when that peak exceeds kPeakFlag (mixed form,
+// matrix-core path).
+constexpr double kPeakFlag = 0.5;
 hipError_t launch_report(const double* prob, int n, const double2* psi, int t,
-                         const unsigned long long* defect_bits, void* report, double* part, hipStream_t s);
+                         const unsigned long long* defect_bits, const double* rot_peak, bool check, void* report,
+                         double* part, hipStream_t s);
 // Final statevector in outcome order: out[m][r] = scale * X[p][r] where row
 // position p of the DFT output holds outcome m (prob_index(p) = m).
 hipError_t launch_gather_state(bool mixed, const void* X, void* out, int n, int t, const DftPlan& plan, double scale,
@@ -418,6 +481,8 @@ struct BatchProblem {
   int32_t n, t;
   const void* U;
   const void* psi;
+  const void* U_src;
+  const void* psi_src;
   double* prob;
   void* report;
   uint64_t ws_offset;
@@ -432,6 +497,9 @@ hipError_t launch_batch_tables(const InstDesc* desc, int ninst, int32_t* tables,
 // readout, report).
 hipError_t launch_batch_elementwise(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                                     bool mixed, int bflags, hipStream_t s);
+// Target-rotation kinds (BK_ROTHASH, BK_ROTPSI, BK_ROTU).
+hipError_t launch_batch_rotate(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
+                               bool mixed, int bflags, hipStream_t s);
 hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                               bool mixed, int bflags, hipStream_t s);
 hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, int bflags,

@@ -25,8 +25,10 @@ FORMS = {"fp64": FORM_FP64, "mixed": FORM_MIXED}
 NO_POLAR = 1
 PREFIX_DOUBLING = 2
 MIX_TARGET = 4
+NO_MIX_TARGET = 8
 REPORT_NOT_UNITARY = 1
 REPORT_NUMERIC = 2
+REPORT_CONCENTRATED = 4
 
 STATUS_NAMES = {
     0: "QPE_OK", 1: "QPE_ERR_ARG", 2: "QPE_ERR_SIZE", 3: "QPE_ERR_ALIGN", 4: "QPE_ERR_WORKSPACE",
@@ -65,8 +67,8 @@ class Problem(ctypes.Structure):
 
 
 REPORT_DTYPE = np.dtype([("unitarity_defect", "<f8"), ("prob_sum", "<f8"), ("psi_norm2", "<f8"),
-                         ("flags", "<u4"), ("reserved", "<u4")])
-REPORT_BYTES = 32
+                         ("input_peak", "<f8"), ("flags", "<u4"), ("reserved", "<u4")])
+REPORT_BYTES = 40
 
 ESTIMATES_DTYPE = np.dtype([("argmax_phase", "<f8"), ("weighted_phase", "<f8"), ("circular_phase", "<f8"),
                             ("prob_sum", "<f8"), ("argmax_index", "<i8"), ("reserved", "<i8")])

@@ -77,7 +77,9 @@ def test_size_limits(L, n, t, code):
 def test_bad_form_flags_count(L):
     out = ctypes.c_size_t()
     assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 2, 0, ctypes.byref(out)) == 1
-    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 8, ctypes.byref(out)) == 1
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 16, ctypes.byref(out)) == 1
+    # forcing the target rotation on (4) and off (8) at once
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 4 | 8, ctypes.byref(out)) == 1
     assert L.qpe_workspace_size(_problems([(8, 2)]), 0, 1, 0, ctypes.byref(out)) == 1
     assert L.qpe_workspace_size(None, 1, 1, 0, ctypes.byref(out)) == 1
 
@@ -93,14 +95,18 @@ def test_check_run(L):
     assert L.qpe_check_run(p, 1, 1, 0, ws + 16, need, None) == 4
     assert L.qpe_check_run(p, 1, 1, 0, None, need, None) == 4
     assert L.qpe_check_run(p, 1, 1, 0, ws, need, ws + 4) == 3
-    # the target rotation (flag 4): with the polar step only
-    assert L.qpe_check_run(p, 1, 1, 4, ws, need, None) == 0
-    assert L.qpe_check_run(p, 1, 1, 4 | 1, ws, need, None) == 8
-    assert L.qpe_check_run(p, 1, 1, 8, ws, need, None) == 1
+    # the target rotation forced on (4) or off (8), with or without the
+    # polar step (1); both at once is an argument error
+    for f in (4, 4 | 1, 8, 8 | 1):
+        assert L.qpe_check_run(p, 1, 1, f, ws, need, None) == 0
+    assert L.qpe_check_run(p, 1, 1, 4 | 8, ws, need, None) == 1
+    assert L.qpe_check_run(p, 1, 1, 16, ws, need, None) == 1
     two = _problems([(8, 2), (8, 2)])
-    assert L.qpe_workspace_size(two, 2, 1, 0, ctypes.byref(out)) == 0
-    assert L.qpe_check_run(two, 2, 1, 4, ws, out.value, None) == 0
-    assert L.qpe_check_run(two, 2, 1, 4 | 1, ws, out.value, None) == 8
+    for f in (4, 4 | 1):
+        # a forced rotation adds launches (table entries) to a batch
+        assert L.qpe_workspace_size(two, 2, 1, f, ctypes.byref(out)) == 0
+        assert L.qpe_check_run(two, 2, 1, f, ws, out.value, None) == 0
+        assert L.qpe_check_run(two, 2, 1, f, ws, out.value - 1, None) == 4
     bad = _problems([(8, 2)])
     bad[0].U = 0x10008
     assert L.qpe_check_run(bad, 1, 1, 0, ws, need, None) == 3

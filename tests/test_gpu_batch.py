@@ -13,7 +13,7 @@ import torch
 
 import oracle.qpe_oracle as O
 from tests.libutil import ensure_built
-from workloads import analytic_problem, config_problems, haar_unitary, make_problem
+from workloads import config_problems, haar_unitary, make_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -65,17 +65,6 @@ def test_batch_uneven_matches_single_and_oracle(qpe, form):
         assert np.array_equal(Pb, single), (n, U.shape[0])
         assert np.abs(Pb - O.qpe_probs(U, psi, n)).max() < tol, (n, U.shape[0])
         assert r["flags"] == 0 and abs(r["prob_sum"] - 1.0) < 1e-6
-
-
-@pytest.mark.parametrize("form", ["mixed", "fp64"])
-def test_batch_no_polar_analytic(qpe, form):
-    cases = [(2, 4, 3), (3, 5, 5), (4, 6, 11), (1, 3, 1), (5, 6, 17)]
-    say("batch analytic no-polar", form, cases)
-    problems = [analytic_problem(n, t, j) for t, n, j in cases]
-    out = qpe.run_batch([(dev(p.U), dev(p.psi), p.n_meas) for p in problems], form, flags=qpe.NO_POLAR)
-    for (t, n, j), P in zip(cases, out):
-        P = host(P)
-        assert abs(P[j << (n - t)] - 1.0) < (1e-6 if form == "mixed" else 1e-10)
 
 
 def test_config4_full_batch(qpe):
@@ -170,3 +159,44 @@ def test_batch_mix_target_matches_single(qpe, form):
         single = host(qpe.run(Ud, pd, n, form, flags=qpe.MIX_TARGET))
         assert np.array_equal(Pb, single), (n, U.shape[0])
         assert np.abs(Pb - O.qpe_probs(U, psi, n)).max() < tol, (n, U.shape[0])
+
+
+@pytest.mark.parametrize("form", ["mixed", "fp64"])
+def test_batch_doubling_tiny_instances(qpe, form):
+    """Prefix doubling in a batch whose instances include n_mat = 0 (a single
+    amplitude in row 0) and n_mat = 1 beside larger ones: against the oracle
+    and bit for bit against single runs."""
+    shapes = [(5, 0), (3, 1), (9, 5), (1, 0), (6, 0), (8, 7), (2, 1), (7, 3)]
+    say("batch doubling with tiny instances", form, shapes)
+    rng = np.random.default_rng(960)
+    probs = []
+    for n, t in shapes:
+        d = 1 << t
+        U = haar_unitary(d, rng)
+        psi = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        psi /= np.linalg.norm(psi)
+        probs.append((U, psi, n))
+    items = [(dev(U), dev(psi), n) for U, psi, n in probs]
+    batch = qpe.run_batch(items, form, flags=qpe.PREFIX_DOUBLING)
+    tol = 1e-6 if form == "mixed" else 1e-12
+    for (U, psi, n), (Ud, pd, _), Pb in zip(probs, items, batch):
+        Pb = host(Pb)
+        assert np.abs(Pb - O.qpe_probs(U, psi, n)).max() < tol, (n, U.shape[0])
+        single = host(qpe.run(Ud, pd, n, form, flags=qpe.PREFIX_DOUBLING))
+        assert np.array_equal(Pb, single), (n, U.shape[0])
+
+
+@pytest.mark.parametrize("flags", [0, 8])
+def test_batch_rotation_default_and_off_match_single(qpe, flags):
+    """Mixed batches with the default rotation (n_mat >= 5 rotated) and with
+    it turned off (QPE_NO_MIX_TARGET): bit for bit equal to single runs,
+    reports equal too."""
+    probs = config_problems("c4", count=16)
+    say("mixed batch, rotation flags", flags)
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    batch, rep = qpe.run_batch(items, "mixed", flags=flags, report=True)
+    for (U, psi, n), p, Pb, r in zip(items, probs, batch, rep):
+        single, rs = qpe.run(U, psi, n, "mixed", flags=flags, report=True)
+        assert np.array_equal(host(Pb), host(single))
+        assert r["input_peak"] == rs["input_peak"] and r["flags"] == rs["flags"] == 0
+        assert np.abs(host(Pb) - O.fejer(p.phis[0], n)).max() < 1e-6

@@ -14,7 +14,7 @@ import torch
 
 import oracle.qpe_oracle as O
 from tests.libutil import ensure_built
-from workloads import analytic_problem, config_problems, haar_unitary, make_problem
+from workloads import config_problems, haar_unitary, make_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -84,11 +84,3 @@ def test_doubling_batch(qpe, form):
         single = host(qpe.run(U, psi, n, form, flags=qpe.PREFIX_DOUBLING))
         assert np.array_equal(P, single)
         assert np.abs(P - O.fejer(p.phis[0], n)).max() < (1e-6 if form == "mixed" else 1e-10)
-
-
-def test_doubling_no_polar_analytic(qpe):
-    for t, n, j in [(2, 4, 3), (3, 5, 5), (4, 6, 11)]:
-        say("doubling analytic no-polar", t, n, j)
-        p = analytic_problem(n, t, j)
-        P = host(qpe.run(dev(p.U), dev(p.psi), n, "mixed", flags=qpe.NO_POLAR | qpe.PREFIX_DOUBLING))
-        assert abs(P[j << (n - t)] - 1.0) < 1e-6
