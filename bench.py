@@ -47,6 +47,12 @@ TRAFFIC = {
                          "profile": "profiles/ctrl_bf16x6_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
+# variants of the split-BF16 controlled product whose counters TRAFFIC holds
+# at n = 16, t = 10 (0 = the built-in choice there, 7 = the same kernel)
+TRAFFIC_VARIANTS = (0, 7)
+CTRL_KERNELS = {0: "k_ctrl_bf16x6_pp2<128,128>", 1: "k_ctrl_bf16x6<64,64>", 2: "k_ctrl_bf16x6_db<128,128>",
+                3: "k_ctrl_bf16x6_db<128,128> (compiler order)", 4: "k_ctrl_bf16x6_tb<128,128>",
+                5: "k_ctrl_bf16x6_bg<128,128>", 6: "k_ctrl_bf16x6_pp<128,128>", 7: "k_ctrl_bf16x6_pp2<128,128>"}
 
 
 def traffic_for_current_kernel():
@@ -71,24 +77,24 @@ CONFIGS = {
 }
 
 
-def bench_batch(a, qpe, torch, config_problems):
-    """Batched workload: all instances in one qpe_run (grouped launches),
-    timed eagerly and as a replayed HIP graph."""
-    probs = config_problems(a.config)
+def measure_batch(qpe, torch, probs, steps, warmup, autotune=True):
+    """A batched workload: all instances in one qpe_run (grouped launches),
+    the batch autotuner first (a few batched runs per variant, outside the
+    timed region), then timed eagerly and as a replayed HIP graph; the same
+    batch in the FP64 form beside it (replayed graph). Each instance's P is
+    checked against the Fejer closed form of its eigenphase (eigenvector
+    inputs)."""
+    import oracle.qpe_oracle as O
     items = [(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas) for p in probs]
     run = qpe.Runner(items, form="mixed")
-    tuned = None
-    if getattr(a, "autotune", False) and not getattr(a, "no_autotune", False):
-        # the batch autotuner picks the grouped kernels' variants (a few
-        # batched runs per variant, before and outside the timed region)
-        tuned = run.autotune(reps=2)
-    for _ in range(a.warmup):
+    tuned = run.autotune(reps=2) if autotune else None
+    for _ in range(warmup):
         run()
     torch.cuda.synchronize()
-    run.ctx.enable_timing(400 * a.steps + 512)
+    run.ctx.enable_timing(400 * steps + 512)
     run.ctx.reset_timing()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         run()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -96,50 +102,70 @@ def bench_batch(a, qpe, torch, config_problems):
     run.ctx.reset_timing()
     graph = qpe.CapturedRun(run)
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         graph()
     torch.cuda.synchronize()
     el_g = time.perf_counter() - t0
     rep = run.reports()
     P_mixed = [P.cpu().numpy() for P in run.probs]
-    # the same batch in the FP64 form (replayed graph), beside it
     run64 = qpe.Runner(items, form="fp64")
     run64()
     torch.cuda.synchronize()
     graph64 = qpe.CapturedRun(run64)
-    steps64 = max(2, a.steps // 2)
+    steps64 = max(2, steps // 2)
     t0 = time.perf_counter()
     for _ in range(steps64):
         graph64()
     torch.cuda.synchronize()
     el64 = time.perf_counter() - t0
-    dP = max(float(np.abs(P64.cpu().numpy() - Pm).max()) for P64, Pm in zip(run64.probs, P_mixed))
+    P64 = [P.cpu().numpy() for P in run64.probs]
+    dP = max(float(np.abs(a - b).max()) for a, b in zip(P64, P_mixed))
+    err_mixed = max(float(np.abs(Pm - O.fejer(p.phis[0], p.n_meas)).max()) for p, Pm in zip(probs, P_mixed))
+    err_fp64 = max(float(np.abs(Pf - O.fejer(p.phis[0], p.n_meas)).max()) for p, Pf in zip(probs, P64))
     count = len(probs)
     flops = sum(4.0 * p.n_meas * (1 << p.n_meas) * (1 << p.n_mat) ** 2 for p in probs)
     g_cnt, g_ms = timing["ctrl_gemm"]
+    mixed_cps = count * steps / el_g
+    fp64_cps = count * steps64 / el64
+    del graph, graph64, run, run64, items
+    return {
+        "instances": count, "steps": steps,
+        "circuits_per_s": round(mixed_cps, 2), "ms_per_batch": round(1e3 * el_g / steps, 3),
+        "eager_ms_per_batch": round(1e3 * el / steps, 3),
+        "fp64_form": {"circuits_per_s": round(fp64_cps, 2), "ms_per_batch": round(1e3 * el64 / steps64, 3),
+                      "steps": steps64, "max_abs_err_vs_fejer": err_fp64},
+        "mixed_over_fp64": round(mixed_cps / fp64_cps, 3),
+        "max_abs_err_mixed_vs_fejer": err_mixed,
+        "max_abs_dP_mixed_vs_fp64": dP,
+        "ctrl_gemm": {"algorithmic_flops_per_batch": flops, "ms_per_batch": round(g_ms / steps, 3),
+                      "achieved_tflops": round(flops / (g_ms / steps / 1e3) / 1e12, 2),
+                      "frac_of_bf16_peak": round(flops / (g_ms / steps / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                      "launches_per_batch": g_cnt // steps},
+        "breakdown": {k: {"launches": c // steps, "ms_per_batch": round(ms / steps, 4)}
+                      for k, (c, ms) in timing.items()},
+        "reports": {"flags_nonzero": int(np.count_nonzero(rep["flags"])),
+                    "max_abs_prob_sum_minus_1": float(np.abs(rep["prob_sum"] - 1.0).max()),
+                    "max_input_peak": float(rep["input_peak"].max())},
+        "autotune": tuned,
+        "graph": True,
+    }
+
+
+def bench_batch(a, qpe, torch, config_problems):
+    """--config c4: the batched workload as the headline line."""
+    probs = config_problems(a.config)
+    b = measure_batch(qpe, torch, probs, a.steps, a.warmup, autotune=not a.no_autotune)
     out = {
         "metric": "QPE circuits/s (mixed form, batched)",
-        "value": round(count * a.steps / el_g, 2),
+        "value": b["circuits_per_s"],
         "unit": "circuits/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(1e3 * el_g / a.steps, 3),
+        "ms_per_step": b["ms_per_batch"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitaries, eigenvector inputs)",
-        "config": {"workload": CONFIGS[a.config], "instances": count, "form": "mixed", "graph": True},
-        "autotune": tuned,
-        "eager_ms_per_step": round(1e3 * el / a.steps, 3),
-        "ctrl_gemm": {"algorithmic_flops_per_step": flops, "ms_per_step": round(g_ms / a.steps, 3),
-                      "achieved_tflops": round(flops / (g_ms / a.steps / 1e3) / 1e12, 2),
-                      "launches_per_step": g_cnt // a.steps},
-        "breakdown": {k: {"launches": c // a.steps, "ms_per_step": round(ms / a.steps, 4)}
-                      for k, (c, ms) in timing.items()},
-        "reports": {"flags_nonzero": int(np.count_nonzero(rep["flags"])),
-                    "max_abs_prob_sum_minus_1": float(np.abs(rep["prob_sum"] - 1.0).max())},
-        "fp64_form": {"circuits_per_s": round(count * steps64 / el64, 2),
-                      "ms_per_step": round(1e3 * el64 / steps64, 3), "steps": steps64},
-        "mixed_over_fp64": round((count * a.steps / el_g) / (count * steps64 / el64), 3),
-        "max_abs_dP_mixed_vs_fp64": dP,
+        "config": {"workload": CONFIGS[a.config], "instances": b["instances"], "form": "mixed", "graph": True},
+        "batched": b,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -205,10 +231,11 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=0, help="timed FP64-form circuits (default steps//2, >=3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the autotuner first (the timed kernels are then the ones it picks; by default the "
-                         "built-in variants run, whose HBM counters the traffic figure refers to)")
-    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (by default it picks the tile variants first, outside the timed "
+                         "region; the timed kernels are the ones it picks)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched c4 leg of the default run")
+    ap.add_argument("--batch-steps", type=int, default=10, help="timed batches of the batched c4 leg")
     ap.add_argument("--study", choices=["precision", "scaling"], default=None,
                     help="precision: the estimator study (section 4.2) over every eigenvector of a 16 x 16 Haar "
                          "unitary for n = --study-n-min .. --study-n-max; scaling: time and device memory "
@@ -411,7 +438,7 @@ def main():
     prob = {"U": torch.from_numpy(p.U).cuda(), "psi": torch.from_numpy(p.psi).cuda(), "n": n}
 
     tuned = {}
-    if a.autotune and not a.no_autotune:
+    if not a.no_autotune:
         # the autotuner picks the tile variants of this operator size (a few
         # circuits per variant, before and outside the timed region)
         ctx = qpe.context(torch.cuda.current_device())
@@ -427,16 +454,20 @@ def main():
     g_cnt, g_ms = timing["ctrl_gemm"]
     avg_s = (g_ms / g_cnt) / 1e3 if g_cnt else float("nan")
     achieved = flops_per_launch / avg_s / 1e12
+    ctx = qpe.context(torch.cuda.current_device())
+    ctrl_variant = ctx.get_variant("ctrl_mixed", t) if t >= 5 else None
     roofline = {
-        "kernel": ("k_ctrl_bf16x6_pp2<128,128> (controlled product, split-BF16 x6 on MFMA)"
-                   if not tuned else "k_ctrl_bf16x6 (variant picked by the autotuner)") if t >= 5 else "k_ctrl_small",
+        "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, 'k_ctrl')} (controlled product, split-BF16 x6 on MFMA; "
+                   f"variant {ctrl_variant})") if t >= 5 else "k_ctrl_small",
         "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
         "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
         "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt,
     }
     # traffic: HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE), or null
-    tr = traffic_for_current_kernel() if (a.config == "c2" and t >= 5 and not tuned) else None
+    # valid for the kernel the counters were taken on: the built-in choice at
+    # this size (variant 0) or the same kernel picked explicitly
+    tr = traffic_for_current_kernel() if (a.config == "c2" and ctrl_variant in TRAFFIC_VARIANTS) else None
     roofline["traffic"] = tr["bytes_per_launch"] if tr else None
     roofline["traffic_detail"] = tr
     breakdown = {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing.items()}
@@ -460,7 +491,7 @@ def main():
         "autotune": tuned or None,
         "breakdown_mixed": breakdown,
         "report_mixed": {"prob_sum": float(rep["prob_sum"]), "unitarity_defect": float(rep["unitarity_defect"]),
-                         "flags": int(rep["flags"])},
+                         "input_peak": float(rep["input_peak"]), "flags": int(rep["flags"])},
         "hbm_state_gbs": round((n * N * d * 8 + 3 * N * d * 8) / (ms_per / 1e3) / 1e9, 1),
     }
 
@@ -493,16 +524,27 @@ def main():
         out["fp64_form"] = {
             "circuits_per_s": round(fsteps / el64, 3), "ms_per_circuit": round(1e3 * el64 / fsteps, 3),
             "steps": fsteps,
-            # algorithmic flops count four real products per complex one; the
-            # kernel executes three (Gauss), so executed = 0.75 x algorithmic
-            "ctrl_gemm": {"achieved": round(ach64, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                          "frac": round(ach64 / PEAK_FP64_TFLOPS, 4),
-                          "executed_frac": round(0.75 * ach64 / PEAK_FP64_TFLOPS, 4),
+            # The kernel forms each complex product from three real ones
+            # (Gauss): 6 executed flop per complex multiply-add. `achieved`
+            # and `frac` count those against the FP64 peak (a true fraction,
+            # <= 1); `algorithmic_tflops` counts 8 flop per multiply-add,
+            # the figure the mixed form's roofline uses, and can exceed the
+            # FP64 peak for that reason.
+            "ctrl_gemm": {"achieved": round(0.75 * ach64, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(0.75 * ach64 / PEAK_FP64_TFLOPS, 4),
+                          "algorithmic_tflops": round(ach64, 2),
                           "avg_launch_ms": round(avg64 * 1e3, 4)},
             "breakdown": {k: {"launches": c, "ms_per_circuit": round(ms / fsteps, 4)}
                           for k, (c, ms) in timing64.items()},
         }
         out["mixed_over_fp64"] = round(value / (fsteps / el64), 3)
+
+    if not a.no_batch and a.config == "c2":
+        # The batched pattern: the 512 uneven instances of the batched
+        # workload in one graph-replayed run, mixed against FP64.
+        out["batched_c4"] = measure_batch(qpe, torch, config_problems("c4"), a.batch_steps, 2,
+                                          autotune=not a.no_autotune)
+        out["batched_c4"]["workload"] = CONFIGS["c4"]
 
     if not a.no_cpu_baseline:
         # CPU baseline leg: the oracle, untouched, on one full circuit of the

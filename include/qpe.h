@@ -76,22 +76,26 @@ enum {
    * from rows [0, 2^k): 2^n - 1 row products instead of n 2^(n-1), each row
    * receiving the same sequence of products as in the gate route. Same P. */
   QPE_PREFIX_DOUBLING = 1u << 1,
-  /* Target rotation (on by default in QPE_FORM_MIXED for n_mat >= 5).
-   * Before the run U <- M U M^T and psi <- M psi with M = H D / sqrt(d): H the
-   * Walsh-Hadamard matrix, D a diagonal of signs derived from a hash of the
-   * bits of U and psi (of four candidate diagonals, the one that leaves the
-   * smallest peak weight max_i |(M psi)_i|^2 / ||psi||^2). M is real
-   * orthogonal, so P(m), a marginal over the target register (section 2,
-   * Fig. 1), is unchanged in exact arithmetic. Why: the mixed form's
-   * matrix-core products round each 16-term sum with an error of up to a
-   * few ulp; for state rows spread over the d components these errors
-   * average out, for rows concentrated on a few basis vectors (e.g. an
-   * eigenvector close to a basis vector) they add up coherently over the n
-   * steps (a loss of total probability of 1.5e-6 to 3.6e-6 at N_meas = 16
-   * to 20 without it). M spreads such inputs. Cost: a few Walsh-Hadamard
-   * passes over U (FP64, no d x d products). qpe_run_state rotates the final
-   * statevector back. QPE_MIX_TARGET forces the rotation on (any form, any
-   * n_mat >= 1); QPE_NO_MIX_TARGET turns it off; both: QPE_ERR_ARG. */
+  /* Target rotation (on by default in QPE_FORM_MIXED for n_mat >= 5 unless
+   * QPE_NO_POLAR is set). Before the run U <- M U M^H and psi <- M psi with
+   * M = D2 H D1 / sqrt(d): H the Walsh-Hadamard matrix, D1 a diagonal of
+   * signs and D2 one of unit phases, both derived from a hash of the bits of
+   * U and psi (of four candidate sign diagonals, the one that leaves the
+   * smallest peak weight max_i |(M psi)_i|^2 / ||psi||^2). M is unitary, so
+   * P(m), a marginal over the target register (section 2, Fig. 1), is
+   * unchanged in exact arithmetic. Why: the mixed form's matrix-core
+   * products round each 16-term sum with an error of up to a few ulp; for
+   * state rows spread over the d components these errors average out, for
+   * rows concentrated on a few basis vectors (e.g. an eigenvector close to
+   * a basis vector) they add up coherently over the n steps (up to 1.9e-6
+   * of total probability at N_meas = 16 to 20 without it). M spreads such
+   * inputs. Cost: a few Walsh-Hadamard passes over U (FP64, no d x d
+   * products). Not a default with QPE_NO_POLAR: for a non-unitary U the
+   * rotated products cancel more (measured on the paper's analytic problem:
+   * errors up to 2.6e-5 rotated against 1.2e-6 unrotated at d = 1024).
+   * qpe_run_state rotates the final statevector back. QPE_MIX_TARGET forces
+   * the rotation on (any form, n_mat >= 1); QPE_NO_MIX_TARGET turns it off;
+   * both: QPE_ERR_ARG. */
   QPE_MIX_TARGET = 1u << 2,
   QPE_NO_MIX_TARGET = 1u << 3
 };

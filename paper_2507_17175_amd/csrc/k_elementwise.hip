@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
     }
     case BK_REPORT:
       if (D.report) {
-        const bool rot = rotate_on(mixed, t, batch_rot_mode(bflags));
+        const bool rot = rotate_on(mixed, t, batch_rot_mode(bflags), polar);
         report_block(D.prob, n, D.psi_src, t, polar ? defect : nullptr,
                      rot ? reinterpret_cast<const double*>(defect + kScratchPeak) : nullptr, mixed && t >= 5,
                      D.report);

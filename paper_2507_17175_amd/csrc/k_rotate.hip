@@ -1,27 +1,31 @@
 // Rotation of the target register (paper section 2: the readout P(m) is the
 // squared norm of the final state marginalised over the target register, so
-// any orthogonal change of that register's basis leaves P unchanged):
+// any unitary change of that register's basis leaves P unchanged):
 //
-//   U' = M U M^T,   psi' = M psi,   M = H D / sqrt(d),
+//   U' = M U M^H,   psi' = M psi,   M = D2 H D1 / sqrt(d),
 //
-// H the d x d Walsh-Hadamard matrix (entries (-1)^popcount(i & j)), D a
-// diagonal of signs. The run then emulates the circuit for (U', psi'), whose
-// state rows are M times the original ones. Why: the matrix cores sum each
-// group of 16 BF16 products with an error of up to a few units in the last
-// place; for state rows spread over many components these errors average
-// out, but a row concentrated on a few basis vectors presents the same large
-// product in every row and the errors add up coherently over the n steps.
-// H D spreads such rows over all d components.
+// H the d x d Walsh-Hadamard matrix (entries (-1)^popcount(i & j)), D1 a
+// diagonal of signs, D2 a diagonal of unit phases. The run then emulates the
+// circuit for (U', psi'), whose state rows are M times the original ones.
+// Why: the matrix cores sum each group of 16 BF16 products with an error of
+// up to a few units in the last place; for state rows spread over many
+// components with unrelated phases these errors average out, but a row
+// concentrated on a few basis vectors presents the same large product in
+// every row and the errors add up coherently over the n steps. H D1 spreads
+// such rows over all d components, and D2 gives the components unrelated
+// phases (H D1 alone maps e_0 to a vector of equal entries +-1/sqrt(d),
+// exact in BF16, whose errors again line up).
 //
-// D is derived from a key, a hash of the bits of U and psi, so no fixed
-// input is concentrated again by the rotation; of four sign patterns derived
-// from the key the one whose psi' has the smallest peak weight
+// The diagonals come from a key, a hash of the bits of U and psi, so no fixed
+// input is concentrated again by the rotation; of four sign patterns D1
+// derived from the key the one whose psi' has the smallest peak weight
 // max_i |psi'_i|^2 / ||psi||^2 is kept, and that weight is reported.
 //
-// Arithmetic is FP64 throughout. M U M^T with the Kronecker identity
-// vec(H X H) = (H (x) H) vec(X) (row-major, H symmetric) is one Walsh-Hadamard
-// transform of length d^2 over the flattened D U D, scaled by 1/d (an exact
-// power of two): passes of at most 8 bits through LDS, additions only, no
+// Arithmetic is FP64 throughout. With the Kronecker identity
+// vec(H X H) = (H (x) H) vec(X) (row-major, H symmetric), M U M^H is one
+// Walsh-Hadamard transform of length d^2 over the flattened D1 U D1, scaled
+// by 1/d (an exact power of two), then each element (r, c) times
+// D2_r conj(D2_c): passes of at most 8 bits through LDS, additions only, no
 // d x d products.
 #include "qpe_internal.hpp"
 
@@ -52,10 +56,27 @@ __device__ inline uint64_t hash_elem(uint64_t h, double2 v) {
   return combine(h, uint64_t(__double_as_longlong(v.y)));
 }
 
-// The diagonal D of a key: entry i is -1 when the top bit of a mix of
+// The sign diagonal D1 of a key: entry i is -1 when the top bit of a mix of
 // (key, i) is set.
 __device__ inline double sign_of(uint64_t key, int64_t i) {
   return (mix64(key + uint64_t(i) * 0xd1b54a32d192ed03ull) >> 63) ? -1.0 : 1.0;
+}
+
+// The phase diagonal D2 of a key: entry i is exp(2 pi i u) with u in [0, 1)
+// from the top 53 bits of another mix of (key, i).
+__device__ inline double2 phase_of(uint64_t key, int64_t i) {
+  const uint64_t h = mix64((key ^ 0x8cb92ba72f3d8dd7ull) + uint64_t(i) * 0xaef17502108ef2d9ull);
+  const double u = double(h >> 11) * 0x1.0p-53;
+  double sv, cv;
+  sincospi(2.0 * u, &sv, &cv);
+  return make_double2(cv, sv);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmul_conj(double2 a, double2 b) {  // a conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
 // Fixed-shape tree over the block's 256 values (deterministic).
@@ -172,25 +193,32 @@ __device__ inline void rot_psi_block(const double2* __restrict__ psi, int t, uns
   }
   // 1 / sqrt(d): an exact power of two for even t
   const double scale = ldexp(1.0, -(t / 2)) * ((t & 1) ? 0.70710678118654752440 : 1.0);
+  const uint64_t key = combine(key0, uint64_t(bestc));
   for (int64_t i = threadIdx.x; i < d; i += kThreads) {
-    const double2 a = v[i];
+    const double2 a = cmul(v[i], phase_of(key, i));
     psi_out[i] = make_double2(a.x * scale, a.y * scale);
   }
   if (threadIdx.x == 0) {
-    scratch[kScratchKey] = combine(key0, uint64_t(bestc));
+    scratch[kScratchKey] = key;
     scratch[kScratchPeak] = (unsigned long long)__double_as_longlong(best);
   }
 }
 
+// Factors a Walsh-Hadamard pass applies to element i of its vector, with
+// d = 2^ts, r = i >> ts, c = i & (d - 1):
+constexpr int kInSign2 = 1;      // on loading, D1_r D1_c (both sides of D1 U D1)
+constexpr int kInConjPhase = 2;  // on loading, conj(D2_c)
+constexpr int kOutPhase2 = 4;    // on storing, D2_r conj(D2_c)
+constexpr int kOutSign = 8;      // on storing, D1_c
+
 // One tile of a Walsh-Hadamard pass over bits [s, s + b) of a vector of
 // 2^Ltot elements. Lines are the index values outside the bit group; a tile
 // holds NL consecutive lines x 2^b, loaded so that consecutive threads touch
-// consecutive addresses. in_sign multiplies element i, on loading, by
-// D[i >> ts] D[i & (2^ts - 1)] (both sides of a d x d operator, d = 2^ts);
-// out_sign multiplies, on storing, by D[i & (2^ts - 1)]; scale on storing.
+// consecutive addresses. `mode` selects the factors above; `scale` is
+// applied on storing.
 template <typename T>
 __device__ inline void wht_pass_tile(const T* __restrict__ in, T* __restrict__ out, int Ltot, int s, int b,
-                                     int64_t tile, uint64_t key, bool in_sign, bool out_sign, int ts, double scale) {
+                                     int64_t tile, uint64_t key, int mode, int ts, double scale) {
   __shared__ double2 lds[kWhtTile + kWhtTile / 2];
   const int lb = min(11 - b, Ltot - b);  // log2 of the lines per tile
   const int NL = 1 << lb, R = 1 << b, pitch = R + 1;
@@ -213,11 +241,12 @@ __device__ inline void wht_pass_tile(const T* __restrict__ in, T* __restrict__ o
     const int64_t i = index(q, ll, g);
     const T a = in[i];
     double2 v = make_double2(double(a.x), double(a.y));
-    if (in_sign) {
+    if (mode & kInSign2) {
       const double sg = sign_of(key, i >> ts) * sign_of(key, i & tmask);
       v.x *= sg;
       v.y *= sg;
     }
+    if (mode & kInConjPhase) v = cmul_conj(v, phase_of(key, i & tmask));
     lds[ll * pitch + g] = v;
   }
   __syncthreads();
@@ -237,7 +266,8 @@ __device__ inline void wht_pass_tile(const T* __restrict__ in, T* __restrict__ o
     const int64_t i = index(q, ll, g);
     double2 v = lds[ll * pitch + g];
     double f = scale;
-    if (out_sign) f *= sign_of(key, i & tmask);
+    if (mode & kOutSign) f *= sign_of(key, i & tmask);
+    if (mode & kOutPhase2) v = cmul_conj(cmul(v, phase_of(key, i >> ts)), phase_of(key, i & tmask));
     T o;
     o.x = decltype(o.x)(v.x * f);
     o.y = decltype(o.y)(v.y * f);
@@ -259,12 +289,12 @@ __global__ void __launch_bounds__(kThreads) k_rot_psi(const double2* __restrict_
   rot_psi_block(psi, t, scratch, psi_out, v);
 }
 
-// Pass q of M U M^T: bits [s, s + b) of the 2t-bit flattened index.
+// Pass q of M U M^H: bits [s, s + b) of the 2t-bit flattened index.
 __global__ void __launch_bounds__(kThreads) k_rot_u_pass(const double2* __restrict__ in, double2* __restrict__ out,
                                                          int t, int s, int b, int first, int last,
                                                          const unsigned long long* __restrict__ scratch) {
   const uint64_t key = scratch[kScratchKey];
-  wht_pass_tile<double2>(in, out, 2 * t, s, b, blockIdx.x, key, first != 0, false, t,
+  wht_pass_tile<double2>(in, out, 2 * t, s, b, blockIdx.x, key, (first ? kInSign2 : 0) | (last ? kOutPhase2 : 0), t,
                          last ? ldexp(1.0, -t) : 1.0);
 }
 
@@ -275,7 +305,8 @@ __global__ void __launch_bounds__(kThreads) k_unrotate_pass(T* __restrict__ stat
                                                             int64_t tile0) {
   const uint64_t key = scratch[kScratchKey];
   const double scale = last ? ldexp(1.0, -(t / 2)) * ((t & 1) ? 0.70710678118654752440 : 1.0) : 1.0;
-  wht_pass_tile<T>(state, state, n + t, s, b, tile0 + blockIdx.x, key, false, last != 0, t, scale);
+  wht_pass_tile<T>(state, state, n + t, s, b, tile0 + blockIdx.x, key,
+                   (s == 0 ? kInConjPhase : 0) | (last ? kOutSign : 0), t, scale);
 }
 
 // ------------------------------------------------------------ batched kernel
@@ -302,8 +333,9 @@ __global__ void __launch_bounds__(kThreads) kb_rotate(int step, const InstDesc* 
     const DftPlan pl = rot_plan(t);
     int s = 0;
     for (int q = 0; q < step; ++q) s += pl.bits[q];
+    const bool last = step == pl.npass - 1;
     wht_pass_tile<double2>(step == 0 ? D.U_src : Ur, Ur, 2 * t, s, pl.bits[step], local, scratch[kScratchKey],
-                           step == 0, false, t, step == pl.npass - 1 ? ldexp(1.0, -t) : 1.0);
+                           (step == 0 ? kInSign2 : 0) | (last ? kOutPhase2 : 0), t, last ? ldexp(1.0, -t) : 1.0);
   }
 }
 

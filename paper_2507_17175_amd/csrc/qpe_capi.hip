@@ -99,7 +99,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
     maxn = p[i].n_meas > maxn ? p[i].n_meas : maxn;
     int np = make_dft_plan(p[i].n_meas).npass;
     maxpass = np > maxpass ? np : maxpass;
-    if (rotate_on(mixed, p[i].n_mat, rot_mode(flags))) {
+    if (rotate_on(mixed, p[i].n_mat, rot_mode(flags), polar)) {
       np = rot_plan(p[i].n_mat).npass;
       maxrot = np > maxrot ? np : maxrot;
     }
@@ -327,8 +327,9 @@ qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, cons
   return QPE_OK;
 }
 
-// Target rotation: Ur = M U M^T and pr = M psi with M = H D / sqrt(d), the
-// key of D and the peak weight of pr in the instance's scratch words.
+// Target rotation: Ur = M U M^H and pr = M psi with M = D2 H D1 / sqrt(d),
+// the key of the diagonals and the peak weight of pr in the instance's
+// scratch words.
 qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* psi, double2* Ur, double2* pr,
                          unsigned long long* scratch) {
   hipStream_t s = ctx->stream;
@@ -360,7 +361,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   QPE_HIP(ctx, launch_zero_u64(defect, 1, s));
   const double2* U0 = static_cast<const double2*>(p.U);
   const double2* psi0 = psi;
-  const bool rot = rotate_on(mixed, t, rot_mode(flags));
+  const bool rot = rotate_on(mixed, t, rot_mode(flags), polar);
   if (rot) {
     // U' goes to A: it is read as V_0 by step 0 and by the first square,
     // which writes B; A is next written by the power step of k = 1 (polar)
@@ -456,7 +457,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       const qpe_problem& q = p[first + i];
       const void* Uq = q.U;
       const void* pq = q.psi;
-      if (rotate_on(mixed, q.n_mat, rot_mode(flags))) {
+      if (rotate_on(mixed, q.n_mat, rot_mode(flags), polar)) {
         // The instance's own idle buffers: the grouped power chain writes its
         // first square to vbuf and its corrected power (or, without the
         // polar step, the square of k = 2) to tbuf, so U' sits in tbuf (read
@@ -862,7 +863,7 @@ QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int f
   QPE_HIP(ctx, launch_gather_state(form == QPE_FORM_MIXED, static_cast<char*>(workspace) + L.state0, state_out, n,
                                    t, make_dft_plan(n), scale, ctx->stream));
   // a rotated run's final state is M times the circuit's: rotate it back
-  if (rotate_on(form == QPE_FORM_MIXED, t, rot_mode(flags)))
+  if (rotate_on(form == QPE_FORM_MIXED, t, rot_mode(flags), !(flags & QPE_NO_POLAR)))
     QPE_HIP(ctx, launch_unrotate_state(form == QPE_FORM_MIXED, state_out, n, t,
                                        reinterpret_cast<const unsigned long long*>(static_cast<char*>(workspace) +
                                                                                    L.scratch),

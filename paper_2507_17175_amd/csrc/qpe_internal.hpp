@@ -148,15 +148,16 @@ __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool p
 }
 
 // Target rotation (paper section 2: P(m) is a marginal over the target
-// register, so an orthogonal change of that register's basis leaves it
-// unchanged): U <- M U M^T, psi <- M psi with M = H D / sqrt(d), H the
-// Walsh-Hadamard matrix and D a diagonal of signs drawn from a hash of U and
-// psi. It is on by default in the mixed form for d >= 32 (the matrix-core
-// path), forced on by QPE_MIX_TARGET and off with QPE_NO_MIX_TARGET.
+// register, so a unitary change of that register's basis leaves it
+// unchanged): U <- M U M^H, psi <- M psi with M = D2 H D1 / sqrt(d), H the
+// Walsh-Hadamard matrix, D1 a diagonal of signs and D2 one of phases, both
+// drawn from a hash of U and psi. On by default in the mixed form for
+// d >= 32 (the matrix-core path) when the polar step treats U as unitary;
+// forced on by QPE_MIX_TARGET and off with QPE_NO_MIX_TARGET.
 enum RotMode { kRotDefault = 0, kRotForce = 1, kRotOff = 2 };
-__host__ __device__ inline bool rotate_on(bool mixed, int t, int mode) {
+__host__ __device__ inline bool rotate_on(bool mixed, int t, int mode, bool polar) {
   if (t == 0 || mode == kRotOff) return false;
-  return mode == kRotForce || (mixed && t >= 5);
+  return mode == kRotForce || (mixed && polar && t >= 5);
 }
 
 // Where V_k lives during a run: 0 = U itself, 1 = vbuf, 2 = tbuf. With the
@@ -260,11 +261,11 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     case BK_ZERO:
       return 1;
     case BK_ROTHASH:
-      return rotate_on(mixed, t, batch_rot_mode(bflags)) ? rot_hash_blocks(t) : 0;
+      return rotate_on(mixed, t, batch_rot_mode(bflags), polar) ? rot_hash_blocks(t) : 0;
     case BK_ROTPSI:
-      return rotate_on(mixed, t, batch_rot_mode(bflags)) ? 1 : 0;
+      return rotate_on(mixed, t, batch_rot_mode(bflags), polar) ? 1 : 0;
     case BK_ROTU: {
-      if (!rotate_on(mixed, t, batch_rot_mode(bflags))) return 0;
+      if (!rotate_on(mixed, t, batch_rot_mode(bflags), polar)) return 0;
       const DftPlan pl = rot_plan(t);
       return step < pl.npass ? cdiv(d * d, kWhtTile) : 0;
     }
@@ -396,12 +397,12 @@ hipError_t launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
 // launch_rot_psi combines them with a hash of psi into the key, tries four
 // sign diagonals derived from it and keeps the one whose M psi has the
 // smallest peak weight max_i |(M psi)_i|^2 / ||psi||^2 (key and peak into
-// scratch, M psi into psi_out); launch_rot_u writes Ur = M U M^T.
+// scratch, M psi into psi_out); launch_rot_u writes Ur = M U M^H.
 hipError_t launch_rot_hash(const double2* U, int t, unsigned long long* scratch, hipStream_t s);
 hipError_t launch_rot_psi(const double2* psi, int t, unsigned long long* scratch, double2* psi_out, hipStream_t s);
 hipError_t launch_rot_u(const double2* U, double2* Ur, int t, const unsigned long long* scratch, hipStream_t s);
 // Undo the rotation on a final statevector (N x d, outcome rows): every row
-// a <- M^T a (complex64 when mixed, else complex128), in place.
+// a <- M^H a (complex64 when mixed, else complex128), in place.
 hipError_t launch_unrotate_state(bool mixed, void* state, int n, int t, const unsigned long long* scratch,
                                  hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,

@@ -90,6 +90,21 @@ def test_analytic_case_no_polar(qpe, form, t, n, j):
     # psi is a unit vector; the run keeps its norm to the same tolerance
     assert abs(float(rep["prob_sum"]) - 1.0) < TOL[form] * 4
     assert abs(float(rep["prob_sum"]) - P.sum()) < 1e-12
+    # x_0 = e_0 is reported as concentrated (it stays exact here: U is upper
+    # triangular, so every state row has one non-zero component)
+    assert rep["flags"] & ~np.uint32(qpe.REPORT_CONCENTRATED) == 0
+
+
+@pytest.mark.parametrize("t,n,j", CASES)
+def test_analytic_forced_rotation(qpe, t, n, j):
+    """QPE_MIX_TARGET with QPE_NO_POLAR: the rotation is not a default for a
+    non-unitary U, but forced on it keeps the Table 2 cases within 1e-6."""
+    say("analytic, forced rotation, mixed", t, n, j)
+    p = analytic_problem(n, t, j)
+    P, rep = qpe.run(dev(p.U), dev(p.psi), n, "mixed", flags=qpe.NO_POLAR | qpe.MIX_TARGET, report=True)
+    P = host(P)
+    e_or, e_ex = _check(P, t, n, j, "mixed")
+    say("max|dP| vs oracle", e_or, "input_peak", float(rep["input_peak"]))
     assert rep["flags"] == 0
 
 
