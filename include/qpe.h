@@ -187,6 +187,23 @@ qpe_status qpe_run_state(qpe_ctx *ctx, const qpe_problem *problem, int form, uns
                          void *workspace, size_t workspace_bytes, void *state_out,
                          qpe_report *report);
 
+/* qpe_run without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). It calls no hipMalloc/hipFree and no
+ * allocating library routine: the workspace is a static device array of
+ * QPE_STATIC_WORKSPACE_BYTES that each device the library runs on holds from
+ * the first qpe_ctx_create on that device until the process ends. Every call
+ * on one device shares that array and keeps the last call's contents (a run
+ * ignores them on entry), so calls that overlap in time on one device (other
+ * streams, other contexts, other host threads) race and give wrong results:
+ * serialise them. Arguments, outputs and errors as qpe_run; problems whose
+ * qpe_workspace_size exceeds QPE_STATIC_WORKSPACE_BYTES: QPE_ERR_WORKSPACE
+ * (qpe_last_error gives both sizes), nothing enqueued; the array's address
+ * unavailable on the device: QPE_ERR_HIP. */
+#define QPE_STATIC_WORKSPACE_BYTES (64u << 20)
+qpe_status qpe_run_static(qpe_ctx *ctx, const qpe_problem *problems, int count, int form,
+                          unsigned flags, qpe_report *report);
+
 /* Host-only pre-flight: the status qpe_run would return for these arguments
  * before it touches the context or the device (QPE_OK if they are valid).
  * Never dereferences device pointers. */

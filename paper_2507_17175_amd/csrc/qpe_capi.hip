@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -550,6 +551,50 @@ QPE_API const char* qpe_version(void) { return "0.1.0"; }
 
 QPE_API const char* qpe_last_error(const qpe_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
+// ---------------------------------------------- static workspace (no allocation)
+//
+// qpe_run_static runs in this array instead of a caller workspace. Each
+// device the library runs on holds its own copy (loaded with the code object,
+// kept until the process ends). In host code the name `scratch` is only a
+// host-side stand-in: its device address on each device comes from
+// hipGetSymbolAddress, taken once per device when the first context on that
+// device is created, and only that address is used afterwards.
+static __device__ __align__(256) unsigned char scratch[QPE_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+hipError_t g_static_err[kMaxDevices] = {};
+bool g_static_tried[kMaxDevices] = {};
+
+// With `device` current: look up the array's address on it (once).
+void fetch_static_workspace(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_tried[device]) return;
+  g_static_tried[device] = true;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_static_ptr[device] = p;
+  } else {
+    g_static_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+    (void)hipGetLastError();  // do not leave the error for the caller's next call
+  }
+}
+
+void* static_workspace(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  *err = g_static_err[device];
+  return g_static_ptr[device];
+}
+}  // namespace
+
 QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
   if (!out) return QPE_ERR_ARG;
   *out = nullptr;
@@ -560,6 +605,12 @@ QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
   if (!c) return QPE_ERR_OOM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  {
+    // set-up of the static workspace on this device (its failure only
+    // affects qpe_run_static, which then reports it)
+    DeviceGuard guard(device);
+    if (guard.ok) fetch_static_workspace(device);
+  }
   *out = c;
   return QPE_OK;
 }
@@ -843,6 +894,24 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
   if (count == 1) return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report);
   return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report);
+}
+
+QPE_API qpe_status qpe_run_static(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
+                                  qpe_report* report) {
+  if (!ctx) return QPE_ERR_ARG;
+  size_t need = 0;
+  qpe_status s = qpe_workspace_size(problems, count, form, flags, &need);
+  if (s != QPE_OK) return s;
+  if (need > size_t(QPE_STATIC_WORKSPACE_BYTES)) {
+    ctx->last_error = "qpe_run_static: these problems need a workspace of " + std::to_string(need) +
+                      " bytes; the static workspace holds " + std::to_string(size_t(QPE_STATIC_WORKSPACE_BYTES));
+    return QPE_ERR_WORKSPACE;
+  }
+  hipError_t e = hipSuccess;
+  void* ws = static_workspace(ctx->device, &e);
+  if (!ws) return hip_fail(ctx, e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+  // qpe_run ignores the workspace's contents on entry and allocates nothing
+  return qpe_run(ctx, problems, count, form, flags, ws, size_t(QPE_STATIC_WORKSPACE_BYTES), report);
 }
 
 QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags,

@@ -43,8 +43,11 @@ EXPORTS = (
     "qpe_status_string", "qpe_last_error", "qpe_version", "qpe_check_run",
     "qpe_ctx_enable_timing", "qpe_ctx_set_timing_mask", "qpe_ctx_reset_timing", "qpe_ctx_read_timing",
     "qpe_kernel_variants", "qpe_ctx_set_variant", "qpe_estimate_workspace_size", "qpe_estimate",
-    "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune", "qpe_autotune_batch",
+    "qpe_run_state", "qpe_ctx_get_variant", "qpe_autotune", "qpe_autotune_batch", "qpe_run_static",
 )
+
+# Size of the static device workspace of qpe_run_static (QPE_STATIC_WORKSPACE_BYTES).
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2, "batch_ctrl": 3, "batch_gemm": 4}
 TUNE_MAX_VARIANTS = 8
@@ -97,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "qpe_ctx_destroy": (st, [vp]),
             "qpe_workspace_size": (st, [ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, ctypes.POINTER(sz)]),
             "qpe_run": (st, [vp, ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, vp, sz, vp]),
+            "qpe_run_static": (st, [vp, ctypes.POINTER(Problem), i32, i32, ctypes.c_uint, vp]),
             "qpe_powers_workspace_size": (st, [i32, ctypes.POINTER(sz)]),
             "qpe_powers": (st, [vp, i32, vp, i32, ctypes.c_uint, vp, vp, sz, vp]),
             "qpe_controlled_step_workspace_size": (st, [i32, i32, i32, ctypes.POINTER(sz)]),
@@ -327,6 +331,37 @@ def run_batch(problems: Sequence[Tuple[torch.Tensor, torch.Tensor, int]], form="
         torch.cuda.current_stream(dev).synchronize()
         r = np.frombuffer(rep.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
         return probs, r
+    return probs
+
+
+def run_batch_static(problems: Sequence[Tuple[torch.Tensor, torch.Tensor, int]], form="mixed", flags: int = 0,
+                     report: bool = False):
+    """run_batch through qpe_run_static: no workspace is allocated (the
+    library's static device array serves as the workspace; problems that need
+    more than STATIC_WORKSPACE_BYTES raise QpeError QPE_ERR_WORKSPACE). The
+    outputs (P, and the report buffer if asked) are still allocated here."""
+    if not problems:
+        return []
+    dev = _dev_index(problems[0][0])
+    arr = (Problem * len(problems))()
+    probs: List[torch.Tensor] = []
+    for i, (U, psi, n) in enumerate(problems):
+        d = U.shape[0]
+        t = d.bit_length() - 1
+        _need(U, torch.complex128, (d, d), "U")
+        _need(psi, torch.complex128, (d,), "psi")
+        p = torch.empty(1 << int(n), dtype=torch.float64, device=U.device)
+        probs.append(p)
+        arr[i].n_meas, arr[i].n_mat = int(n), t
+        arr[i].U, arr[i].psi, arr[i].prob = U.data_ptr(), psi.data_ptr(), p.data_ptr()
+    L = load_library()
+    ctx = context(dev)
+    rep = torch.empty(REPORT_BYTES * len(problems), dtype=torch.uint8, device=f"cuda:{dev}") if report else None
+    _check(L.qpe_run_static(ctx.handle, arr, len(problems), _form(form), flags,
+                            rep.data_ptr() if rep is not None else None), "qpe_run_static", ctx.handle)
+    if report:
+        torch.cuda.current_stream(dev).synchronize()
+        return probs, np.frombuffer(rep.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
     return probs
 
 
