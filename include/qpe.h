@@ -55,11 +55,15 @@ typedef enum qpe_status {
 
 /* Arithmetic form of the statevector path.
  *  QPE_FORM_FP64 : complex128 state; FP64 matrix-core GEMMs throughout.
- *  QPE_FORM_MIXED: complex64 state; the controlled products run as split
- *                  BF16 matrix-core products (three BF16 pieces of each
- *                  operand, six partial products) accumulated in FP32; the
- *                  inverse QFT runs in FP32 and the readout sums in FP64;
- *                  the target register is rotated first (QPE_MIX_TARGET).
+ *  QPE_FORM_MIXED: complex64 state; the controlled products run on the
+ *                  matrix cores as split products accumulated in FP32: the
+ *                  state (scaled by a power of two) and the operator
+ *                  (scaled by 2^14) as two FP16 pieces each, three partial
+ *                  products (QPE_SPLIT_BF16, and runs without the polar
+ *                  step: three BF16 pieces each, six partial products);
+ *                  the inverse QFT runs in FP32 and the readout sums in
+ *                  FP64; the target register is rotated first
+ *                  (QPE_MIX_TARGET).
  * In both forms the powers U^(2^k) are formed in FP64. */
 typedef enum qpe_form { QPE_FORM_FP64 = 0, QPE_FORM_MIXED = 1 } qpe_form;
 
@@ -97,7 +101,15 @@ enum {
    * the rotation on (any form, n_mat >= 1); QPE_NO_MIX_TARGET turns it off;
    * both: QPE_ERR_ARG. */
   QPE_MIX_TARGET = 1u << 2,
-  QPE_NO_MIX_TARGET = 1u << 3
+  QPE_NO_MIX_TARGET = 1u << 3,
+  /* QPE_FORM_MIXED: run the controlled products as split-BF16 products
+   * (three BF16 pieces per operand, six piece products) instead of the
+   * default split-FP16 ones (two FP16 pieces per operand, three piece
+   * products: half the matrix-core work). Without the polar step
+   * (QPE_NO_POLAR) the split-BF16 scheme always runs: the FP16 pieces are
+   * scaled for the row norms a unitary U keeps, and a non-unitary U can
+   * grow them past the FP16 range. */
+  QPE_SPLIT_BF16 = 1u << 4
 };
 
 /* Report flags (qpe_report.flags). */

@@ -59,11 +59,64 @@ __device__ inline void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
   l = (__bf16)r2;
 }
 
-__device__ inline bf16x8 negate(bf16x8 v) {
+template <typename V>
+__device__ inline V negate(V v) {
   u32x4 u = __builtin_bit_cast(u32x4, v);
   u ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-  return __builtin_bit_cast(bf16x8, u);
+  return __builtin_bit_cast(V, u);
 }
+
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(_Float16)))) _Float16 f16x4;
+
+// Arithmetic schemes of the split products. Each operand component is a sum
+// of P pieces in a 16-bit format; of the P x P piece products the pairs
+// (PA[c], PB[c]), c < NPAIR, are kept, in that order (smallest first), and
+// accumulated in FP32 by the matrix cores.
+//
+// Bf16x6: three BF16 pieces per operand (RNE of the running residual), the
+// six pairs with index sum <= 2.
+struct Bf16x6 {
+  typedef bf16x8 v8;
+  typedef bf16x4 v4;
+  typedef __bf16 elem;
+  static constexpr int P = 3, NPAIR = 6;
+  static constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
+  static constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
+  // issue plan of the ping-pong matrix phase (one MFMA, then this many
+  // vector ALU ops, for kValuGroups MFMAs; then LDS writes and loads)
+  static constexpr int kValuGroups = 26, kValuPer = 3, kDsGroups = 3;
+  __device__ static void split(float x, float, elem (&o)[3]) { split3(x, o[0], o[1], o[2]); }
+  __device__ static f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static float out_scale(float) { return 1.0f; }
+};
+
+// F16x3: the state scaled by sigma and the operator by 2^14 (powers of two,
+// chosen so that no piece overflows FP16 and the low pieces stay normal for
+// all but negligible elements), two FP16 pieces each (x = h + l, l the RNE of
+// x - h), the three pairs lh, hl, hh; the FP32 sum is scaled back by
+// 1 / (sigma 2^14). The dropped l l term is below 2^-22 relative, the
+// representation errors 2^-22 each.
+struct F16x3 {
+  typedef f16x8 v8;
+  typedef f16x4 v4;
+  typedef _Float16 elem;
+  static constexpr int P = 2, NPAIR = 3;
+  static constexpr int PA[3] = {1, 0, 0};
+  static constexpr int PB[3] = {0, 1, 0};
+  static constexpr int kValuGroups = 8, kValuPer = 2, kDsGroups = 2;
+  __device__ static void split(float x, float sigma, elem (&o)[2]) {
+    const float y = x * sigma;  // exact: sigma is a power of two
+    o[0] = (_Float16)y;
+    o[1] = (_Float16)(y - (float)o[0]);  // y - h is exact in FP32
+  }
+  __device__ static f32x16 mfma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static float out_scale(float sigma) { return 1.0f / (sigma * float(kOpScaleF16)); }
+};
 
 __device__ inline int2 xcd_tile(int tiles_m, int tiles_n) {
   const int total = tiles_m * tiles_n;
@@ -128,12 +181,46 @@ __device__ __forceinline__ void mma_pair(int c, f32x16 (&acc_re)[FM][FN], f32x16
     }
 }
 
+// The products of one K chunk of 16 for a scheme: for each kept piece pair,
+// four real products per complex one (re += a.re w.re + a.im (-w.im),
+// im += a.re w.im + a.im w.re), in the order of mma_bf16x6.
+template <class S, int FM, int FN>
+__device__ __forceinline__ void mma_pair_s(int c, f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
+                                           const typename S::v8 (&av)[FM][2 * S::P],
+                                           const typename S::v8 (&bv)[FN][2 * S::P],
+                                           const typename S::v8 (&bneg)[FN][S::P]) {
+  const int pa = S::PA[c], pb = S::PB[c];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+      acc_re[x][y] = S::mfma(av[x][2 * pa], bv[y][2 * pb], acc_re[x][y]);
+      acc_im[x][y] = S::mfma(av[x][2 * pa], bv[y][2 * pb + 1], acc_im[x][y]);
+    }
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+      acc_re[x][y] = S::mfma(av[x][2 * pa + 1], bneg[y][pb], acc_re[x][y]);
+      acc_im[x][y] = S::mfma(av[x][2 * pa + 1], bv[y][2 * pb], acc_im[x][y]);
+    }
+}
+
+template <class S, int FM, int FN, int C0 = 0>
+__device__ __forceinline__ void mma_pieces(f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
+                                           const typename S::v8 (&av)[FM][2 * S::P],
+                                           const typename S::v8 (&bv)[FN][2 * S::P],
+                                           const typename S::v8 (&bneg)[FN][S::P]) {
+#pragma unroll
+  for (int c = C0; c < S::NPAIR; ++c) mma_pair_s<S, FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+}
+
 // Output layout of the 32x32 MFMA: lane l, element v holds row
 // 8 * (v / 4) + 4 * (l / 32) + v % 4, column l % 32 of the block.
 template <int FM, int FN>
 __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const f32x16 (&acc_im)[FM][FN],
                                            float2* buf0, float2* buf1, int M, int d, int k, uint64_t pmask, int row0,
-                                           int col0, int lane) {
+                                           int col0, int lane, float oscale = 1.0f) {
 #pragma unroll
   for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -143,25 +230,26 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc_re)[FM][FN], const
       int64_t j = step_row(gi, k, pmask);
       float2* dst = (src_buffer(j, pmask) ? buf0 : buf1) + j * d + col0 + (lane & 31);
 #pragma unroll
-      for (int y = 0; y < FN; ++y) dst[32 * y] = make_float2(acc_re[x][y][v], acc_im[x][y][v]);
+      for (int y = 0; y < FN; ++y) dst[32 * y] = make_float2(acc_re[x][y][v] * oscale, acc_im[x][y][v] * oscale);
     }
 }
 
 // ----------------------------------------------------------------- variant 2
-template <int BM, int BN, int WM, int WN, bool IL = true, int C0 = 0>
+template <class S, int BM, int BN, int WM, int WN, bool IL = true, int C0 = 0>
 __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                              const uint16_t* __restrict__ planes, int n, int t, int k,
-                                             uint64_t pmask, int tile_m, int tile_n) {
+                                             uint64_t pmask, int tile_m, int tile_n, float sigma = 1.0f) {
+  constexpr int NP = 2 * S::P;  // planes per operand (pieces x re/im)
   constexpr int NT = 512;
   static_assert(WM * WN == 8, "8 waves");
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
   constexpr int KS = 16;       // complex K per slab
-  constexpr int ROW = 24;      // padded LDS row in bf16 (48 bytes)
+  constexpr int ROW = 24;      // padded LDS row in 16-bit elements (48 bytes)
   constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
-  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int BUF = NP * (A_PLANE + B_PLANE);
   constexpr int CA = BM * KS / 4 / NT;  // 4-complex A chunks per thread
-  constexpr int NB = 12 * BN;              // 16-byte B chunks per slab
+  constexpr int NB = 2 * NP * BN;          // 16-byte B chunks per slab
   constexpr int CB = (NB + NT - 1) / NT;   // per thread (the last one guarded)
   static_assert(CA >= 1 && CA * NT * 4 == BM * KS, "tile/thread mismatch");
 
@@ -208,21 +296,19 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
   };
 
   // The split of the prefetched A slab, one complex column u (0..3) of each
-  // thread's 4-complex chunk at a time, into pieces pc (re/im x hi/mid/lo).
-  bf16x4 pc[CA][6];
+  // thread's 4-complex chunk at a time, into pieces pc (plane 2 piece + re/im).
+  typename S::v4 pc[CA][NP];
   auto split_part = [&](int u) {
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
       const float4 w = ra[q][u >> 1];
-      __bf16 h, m, l;
-      split3((u & 1) ? w.z : w.x, h, m, l);  // real part
-      pc[q][0][u] = h;
-      pc[q][2][u] = m;
-      pc[q][4][u] = l;
-      split3((u & 1) ? w.w : w.y, h, m, l);  // imaginary part
-      pc[q][1][u] = h;
-      pc[q][3][u] = m;
-      pc[q][5][u] = l;
+      typename S::elem o[S::P];
+      S::split((u & 1) ? w.z : w.x, sigma, o);  // real part
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2][u] = o[pc2];
+      S::split((u & 1) ? w.w : w.y, sigma, o);  // imaginary part
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2 + 1][u] = o[pc2];
     }
   };
   auto write_a = [&](int b) {
@@ -232,8 +318,8 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       int c = tid + q * NT;
       int r = c / 4, kq = c & 3;
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
+      for (int pl = 0; pl < NP; ++pl)
+        *reinterpret_cast<typename S::v4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
     }
   };
   auto write_b = [&](int b) {
@@ -243,7 +329,7 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       int idx = tid + q * NT;
       if (NB % NT != 0 && idx >= NB) break;
       int pl = idx / (BN * 2), w = idx % (BN * 2);
-      *reinterpret_cast<u32x4*>(base + 6 * A_PLANE + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
+      *reinterpret_cast<u32x4*>(base + NP * A_PLANE + pl * B_PLANE + (w >> 1) * ROW + 8 * (w & 1)) = rb[q];
     }
   };
   auto store_lds = [&](int b) {
@@ -273,20 +359,20 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
 
   for (int s = 0; s < nk; ++s) {
     const uint16_t* base = lds + (s & 1) * BUF;
-    bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+    typedef typename S::v8 V8;
+    V8 av[FM][NP], bv[FN][NP], bneg[FN][S::P];
 #pragma unroll
     for (int x = 0; x < FM; ++x)
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+      for (int pl = 0; pl < NP; ++pl)
+        av[x][pl] = *reinterpret_cast<const V8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        bv[y][pl] =
-            *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+      for (int pl = 0; pl < NP; ++pl)
+        bv[y][pl] = *reinterpret_cast<const V8*>(base + NP * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
 #pragma unroll
-      for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
+      for (int pc = 0; pc < S::P; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
     }
     // The store of slab s+1 and the loads of slab s+2 are unconditional: the
     // last iteration writes the idle buffer (read in slab nk-2, which every
@@ -298,8 +384,8 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
       // runs that vector work while the matrix cores are still busy,
       // instead of after the last MFMA of the slab.
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        if (c >= C0) mma_pair<FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+      for (int c = 0; c < S::NPAIR; ++c) {
+        if (c >= C0) mma_pair_s<S, FM, FN>(c, acc_re, acc_im, av, bv, bneg);
         __builtin_amdgcn_sched_barrier(0);
         if (c == 0) write_b(nb);
         if (c < 2) {
@@ -311,14 +397,14 @@ __device__ __forceinline__ void ctrl_db_tile(float2* __restrict__ buf0, float2* 
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
-      mma_bf16x6<FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
+      mma_pieces<S, FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
       store_lds(nb);
       load_global(ns);
     }
     __syncthreads();
   }
 
-  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane, S::out_scale(sigma));
 }
 
 template <int BM, int BN, int WM, int WN, bool IL = true, int C0 = 0>
@@ -327,7 +413,16 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_db(float2* __restrict__ buf
                                                          uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_db_tile<BM, BN, WM, WN, IL, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_db_tile<Bf16x6, BM, BN, WM, WN, IL, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_f16x3_db(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                        const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                        uint64_t pmask, const float* __restrict__ sigma) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_db_tile<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y, *sigma);
 }
 
 // ----------------------------------------------------------------- variant 6
@@ -503,20 +598,21 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp(float2* __restrict__ buf
 // phase of slab s is phase 2s+g, its matrix phase 2s+1+g): its rows of
 // buffer (s+1)&1 are written in phase 2s+1+g, read in 2s+2+g and were last
 // read in 2s-2+g; the operator half is handled as in variant 6.
-template <int BM, int BN, int WM, int WN>
+template <class S, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                               const uint16_t* __restrict__ planes, int n, int t, int k,
-                                              uint64_t pmask, int tile_m, int tile_n) {
+                                              uint64_t pmask, int tile_m, int tile_n, float sigma = 1.0f) {
   constexpr int NG = 256;  // threads per group (half of the 512-thread workgroup)
+  constexpr int NP = 2 * S::P;
   static_assert(WM == 2 && WN == 4, "a group is one row half of the tile");
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
   constexpr int KS = 16;
   constexpr int ROW = 24;
   constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
-  constexpr int BUF = 6 * (A_PLANE + B_PLANE);
+  constexpr int BUF = NP * (A_PLANE + B_PLANE);
   constexpr int CA = TM * KS / 4 / NG;  // 4-complex chunks of the group's rows per thread
-  constexpr int NB = 12 * BN / 2;       // 16-byte operator chunks per group
+  constexpr int NB = 2 * NP * BN / 2;   // 16-byte operator chunks per group
   constexpr int CB = (NB + NG - 1) / NG;
   static_assert(CA >= 1 && CA * NG * 4 == TM * KS, "tile/thread mismatch");
   static_assert(NB % NG == 0, "operator chunks per group");
@@ -560,20 +656,18 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
                                               8 * (w & 1));
     }
   };
-  bf16x4 pc[CA][6];
+  typename S::v4 pc[CA][NP];
   auto split_part = [&](int u) {
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
       const float4 w = ra[q][u >> 1];
-      __bf16 h, m, l;
-      split3((u & 1) ? w.z : w.x, h, m, l);
-      pc[q][0][u] = h;
-      pc[q][2][u] = m;
-      pc[q][4][u] = l;
-      split3((u & 1) ? w.w : w.y, h, m, l);
-      pc[q][1][u] = h;
-      pc[q][3][u] = m;
-      pc[q][5][u] = l;
+      typename S::elem o[S::P];
+      S::split((u & 1) ? w.z : w.x, sigma, o);
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2][u] = o[pc2];
+      S::split((u & 1) ? w.w : w.y, sigma, o);
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2 + 1][u] = o[pc2];
     }
   };
   auto write_a = [&](int b) {
@@ -583,12 +677,12 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
       int c = tg + q * NG;
       int r = wi0 + c / 4, kq = c & 3;
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        *reinterpret_cast<bf16x4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
+      for (int pl = 0; pl < NP; ++pl)
+        *reinterpret_cast<typename S::v4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
     }
   };
   auto write_b = [&](int b) {
-    uint16_t* base = lds + b * BUF + 6 * A_PLANE;
+    uint16_t* base = lds + b * BUF + NP * A_PLANE;
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
       int idx = grp * NB + tg + q * NG;
@@ -628,41 +722,44 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
     // memory phase: fragments of slab s, the group's operator chunks of
     // slab s+1 (unconditional, as in the other kernels), loads of slab s+2
     const uint16_t* base = lds + (s & 1) * BUF;
-    bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+    typedef typename S::v8 V8;
+    V8 av[FM][NP], bv[FN][NP], bneg[FN][S::P];
 #pragma unroll
     for (int x = 0; x < FM; ++x)
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        av[x][pl] = *reinterpret_cast<const bf16x8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+      for (int pl = 0; pl < NP; ++pl)
+        av[x][pl] = *reinterpret_cast<const V8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
 #pragma unroll
     for (int y = 0; y < FN; ++y)
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
-        bv[y][pl] =
-            *reinterpret_cast<const bf16x8*>(base + 6 * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+      for (int pl = 0; pl < NP; ++pl)
+        bv[y][pl] = *reinterpret_cast<const V8*>(base + NP * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
     write_b(nb);
     load_b(ns);
 #pragma unroll
     for (int y = 0; y < FN; ++y)
 #pragma unroll
-      for (int pc2 = 0; pc2 < 3; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+      for (int pc2 = 0; pc2 < S::P; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
     // matrix phase, with the split and store of the group's rows of slab s+1
     // spread thinly between the MFMAs (one MFMA, then up to three VALU ops)
-    mma_bf16x6<FM, FN>(acc_re, acc_im, av, bv, bneg);
+    mma_pieces<S, FM, FN>(acc_re, acc_im, av, bv, bneg);
 #pragma unroll
     for (int u = 0; u < 4; ++u) split_part(u);
     write_a(nb);
     load_a(ns);
+    constexpr int kMfma = FM * FN * 4 * S::NPAIR;
+    constexpr int kRest = kMfma - S::kValuGroups - S::kDsGroups - 2;
+    static_assert(kRest >= 0, "issue plan longer than the slab's MFMAs");
 #pragma unroll
-    for (int i = 0; i < 26; ++i) {
+    for (int i = 0; i < S::kValuGroups; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, S::kValuPer, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < S::kDsGroups; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
     }
@@ -671,14 +768,14 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 17, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
   }
   if (grp == 0) __syncthreads();
 
-  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane, S::out_scale(sigma));
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -687,7 +784,16 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp2(float2* __restrict__ bu
                                                           uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_pp2_tile<BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_pp2_tile<Bf16x6, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_f16x3_pp2(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                         const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                         uint64_t pmask, const float* __restrict__ sigma) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_pp2_tile<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y, *sigma);
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -1050,22 +1156,23 @@ __global__ void __launch_bounds__(512) k_ctrl_bf16x6_bg(float2* __restrict__ buf
 }
 
 // ----------------------------------------------------------------- variant 1
-template <int BM, int BN, int WM, int WN, int C0 = 0>
+template <class S, int BM, int BN, int WM, int WN, int C0 = 0>
 __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                              const uint16_t* __restrict__ planes, int n, int t, int k,
-                                             uint64_t pmask, int tile_m, int tile_n) {
+                                             uint64_t pmask, int tile_m, int tile_n, float sigma = 1.0f) {
   constexpr int NT = 256;
+  constexpr int NP = 2 * S::P;
   constexpr int KS = 32;   // complex K per slab (two operator-plane blocks)
-  constexpr int ROW = 40;  // padded LDS row in bf16 (80 bytes)
+  constexpr int ROW = 40;  // padded LDS row in 16-bit elements (80 bytes)
   static_assert(WM * WN == 4, "4 waves");
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 32, FN = TN / 32;
   constexpr int CA = BM * 4 / NT;      // 8-complex A chunks per thread
-  constexpr int CB = 6 * BN * 4 / NT;  // 16-byte B chunks per thread
+  constexpr int CB = NP * BN * 4 / NT;  // 16-byte B chunks per thread
   static_assert(CA >= 1 && CB >= 1, "tile too small");
 
-  __shared__ __attribute__((aligned(16))) uint16_t As[6 * BM * ROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[6 * BN * ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t As[NP * BM * ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NP * BN * ROW];
 
   const int d = 1 << t;
   const int64_t dd = int64_t(d) * d;
@@ -1111,25 +1218,24 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
     for (int q = 0; q < CA; ++q) {
       int c = tid + q * NT;
       int r = c / 4, kc = c & 3;
-      bf16x8 pc[6];
+      typename S::v8 pc[NP];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         float v[4] = {ra[q][u].x, ra[q][u].y, ra[q][u].z, ra[q][u].w};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          __bf16 a, b, cc;
-          split3(v[2 * h], a, b, cc);
-          pc[0][2 * u + h] = a;
-          pc[2][2 * u + h] = b;
-          pc[4][2 * u + h] = cc;
-          split3(v[2 * h + 1], a, b, cc);
-          pc[1][2 * u + h] = a;
-          pc[3][2 * u + h] = b;
-          pc[5][2 * u + h] = cc;
+          typename S::elem o[S::P];
+          S::split(v[2 * h], sigma, o);
+#pragma unroll
+          for (int pc2 = 0; pc2 < S::P; ++pc2) pc[2 * pc2][2 * u + h] = o[pc2];
+          S::split(v[2 * h + 1], sigma, o);
+#pragma unroll
+          for (int pc2 = 0; pc2 < S::P; ++pc2) pc[2 * pc2 + 1][2 * u + h] = o[pc2];
         }
       }
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x8*>(&As[(pl * BM + r) * ROW + 8 * kc]) = pc[pl];
+      for (int pl = 0; pl < NP; ++pl)
+        *reinterpret_cast<typename S::v8*>(&As[(pl * BM + r) * ROW + 8 * kc]) = pc[pl];
     }
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
@@ -1162,21 +1268,22 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const int ko = kk * 16 + lk;
-      bf16x8 av[FM][6], bv[FN][6], bneg[FN][3];
+      typedef typename S::v8 V8;
+      V8 av[FM][NP], bv[FN][NP], bneg[FN][S::P];
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int pl = 0; pl < 6; ++pl)
-          av[x][pl] = *reinterpret_cast<const bf16x8*>(&As[(pl * BM + wi0 + 32 * x + lr) * ROW + ko]);
+        for (int pl = 0; pl < NP; ++pl)
+          av[x][pl] = *reinterpret_cast<const V8*>(&As[(pl * BM + wi0 + 32 * x + lr) * ROW + ko]);
 #pragma unroll
       for (int y = 0; y < FN; ++y) {
 #pragma unroll
-        for (int pl = 0; pl < 6; ++pl)
-          bv[y][pl] = *reinterpret_cast<const bf16x8*>(&Bs[(pl * BN + wj0 + 32 * y + lr) * ROW + ko]);
+        for (int pl = 0; pl < NP; ++pl)
+          bv[y][pl] = *reinterpret_cast<const V8*>(&Bs[(pl * BN + wj0 + 32 * y + lr) * ROW + ko]);
 #pragma unroll
-        for (int pc = 0; pc < 3; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
+        for (int pc = 0; pc < S::P; ++pc) bneg[y][pc] = negate(bv[y][2 * pc + 1]);
       }
-      mma_bf16x6<FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
+      mma_pieces<S, FM, FN, C0>(acc_re, acc_im, av, bv, bneg);
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -1185,7 +1292,7 @@ __device__ __forceinline__ void ctrl_v1_tile(float2* __restrict__ buf0, float2* 
     }
   }
 
-  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane);
+  store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane, S::out_scale(sigma));
 }
 
 template <int BM, int BN, int WM, int WN, int C0 = 0>
@@ -1194,7 +1301,16 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
               int k, uint64_t pmask) {
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
-  ctrl_v1_tile<BM, BN, WM, WN, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+  ctrl_v1_tile<Bf16x6, BM, BN, WM, WN, C0>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_ctrl_f16x3(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16_t* __restrict__ planes, int n, int t,
+             int k, uint64_t pmask, const float* __restrict__ sigma) {
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const int2 tile = xcd_tile(tiles_m, tiles_n);
+  ctrl_v1_tile<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y, *sigma);
 }
 
 // Grouped controlled step k over the instances of a launch table; the tile
@@ -1205,7 +1321,7 @@ k_ctrl_bf16x6(float2* __restrict__ buf0, float2* __restrict__ buf1, const uint16
 // `step` instead: X (complex64, in tbuf) rows [0, d) times the split planes of
 // E, written to gbuf, through the prefix-doubling mapping of a t+1 qubit
 // register.
-template <int KIND, bool INSTEP = false>
+template <int KIND, bool INSTEP = false, bool F16 = false>
 __global__ void __launch_bounds__(KIND == BK_CTRL_M32 || KIND == BK_NS_M32 ? 256 : 512)
 kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags,
               int64_t tile0) {
@@ -1237,23 +1353,51 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
   const int tiles_n = (1 << D.t) / BN;
   const int tm = int(local / tiles_n), tn = int(local % tiles_n);
   constexpr int C0 = NS ? 3 : 0;  // the Newton-Schulz product needs three piece pairs
+  static_assert(!(NS && F16), "the Newton-Schulz product runs in split BF16");
+  typedef typename std::conditional<F16, F16x3, Bf16x6>::type S;
+  float sigma = 1.0f;
+  if constexpr (F16) sigma = *reinterpret_cast<const float*>(D.ws + L.scratch + 8 * kScratchSigma);
   if constexpr (BN == 32)
-    ctrl_v1_tile<128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_v1_tile<S, 128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else if constexpr (BN == 64)
-    ctrl_db_tile<128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_db_tile<S, 128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else if constexpr (NS || INSTEP)
-    ctrl_db_tile<128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_db_tile<S, 128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else
-    ctrl_pp2_tile<128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn);
+    ctrl_pp2_tile<S, 128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
 }
 
-template <int NT, typename K>
+template <int NT, typename K, typename... X>
 hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
-                  uint64_t pmask, hipStream_t s) {
+                  uint64_t pmask, hipStream_t s, X... extra) {
   int M = 1 << (n - 1);
   int tiles = ((M + BM - 1) / BM) * ((1 << t) / BN);
-  hipLaunchKernelGGL(kernel, dim3(tiles), dim3(NT), 0, s, buf0, buf1, planes, n, t, k, pmask);
+  hipLaunchKernelGGL(kernel, dim3(tiles), dim3(NT), 0, s, buf0, buf1, planes, n, t, k, pmask, extra...);
   return hipGetLastError();
+}
+
+// Split-FP16 controlled step: the tile choices of the default split-BF16
+// path (variant 1: the 4-wave kernel throughout, 2: the in-step schedule
+// for every size, 7: ping-pong for d >= 128; the BF16-only designs 3-6 fall
+// back to the default).
+hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
+                           hipStream_t s, int variant, const float* sigma) {
+  if (variant == 1) {
+    if (t >= 7) return launch<256>(k_ctrl_f16x3<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+    if (t == 6) return launch<256>(k_ctrl_f16x3<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+    if (t == 5) return launch<256>(k_ctrl_f16x3<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+    return hipErrorInvalidValue;
+  }
+  const int64_t big_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
+  if (variant != 2 && variant != 7 && t >= 6 && big_tiles < 256)
+    return launch<256>(k_ctrl_f16x3<64, 64, 2, 2>, 64, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  if (t >= 7 && (variant == 7 || (variant != 2 && big_tiles >= 2048)))
+    return launch<512>(k_ctrl_f16x3_pp2<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  if (t >= 7)
+    return launch<512>(k_ctrl_f16x3_db<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  if (t == 6) return launch<512>(k_ctrl_f16x3_db<128, 64, 4, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  if (t == 5) return launch<256>(k_ctrl_f16x3<128, 32, 4, 1>, 128, 32, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -1261,7 +1405,8 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 int ctrl_mixed_variants() { return 7; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
-                             hipStream_t s, int variant) {
+                             hipStream_t s, int variant, const float* sigma_f16) {
+  if (sigma_f16) return launch_ctrl_f16(buf0, buf1, planes, n, t, k, pmask, s, variant, sigma_f16);
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);
@@ -1340,6 +1485,32 @@ hipError_t launch_ns_product(float2* x32, float2* xe, const uint16_t* planes, in
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
                                    int bflags, hipStream_t s) {
   const int p = bflags;
+  if (bflags & kBatchF16) {
+    switch (kind) {
+      case BK_CTRL_M32:
+        return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+          hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M32, false, true>), dim3(g), dim3(256), 0, s, step, desc, table, p,
+                             b);
+        });
+      case BK_CTRL_M64:
+        return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+          hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M64, false, true>), dim3(g), dim3(512), 0, s, step, desc, table, p,
+                             b);
+        });
+      case BK_CTRL_M128:
+        if (bflags & kBatchCtrlInStep)
+          return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+            hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M128, true, true>), dim3(g), dim3(512), 0, s, step, desc, table,
+                               p, b);
+          });
+        return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+          hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M128, false, true>), dim3(g), dim3(512), 0, s, step, desc, table, p,
+                             b);
+        });
+      default:
+        break;  // the Newton-Schulz kinds run in split BF16
+    }
+  }
   switch (kind) {
     case BK_CTRL_M32:
       return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {

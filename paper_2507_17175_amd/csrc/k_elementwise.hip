@@ -107,11 +107,70 @@ __device__ inline void split_value(double2 v, uint16_t* __restrict__ planes, int
   }
 }
 
+// x rounded to the nearest FP16 value, ties to even (|x| below the FP16
+// overflow threshold): the FP16 grid spacing is 2^(e - 10) for |x| in
+// [2^e, 2^(e+1)), e >= -14, and 2^-24 below 2^-14 (subnormals).
+__device__ inline double f16_round(double x) {
+  const double a = fabs(x);
+  if (a < 0x1p-14) return rint(x * 0x1p24) * 0x1p-24;
+  const double q = ldexp(1.0, ilogb(a) - 10);
+  return rint(x / q) * q;
+}
+
+__device__ inline uint16_t f16_bits(double exact_f16) {
+  return __builtin_bit_cast(uint16_t, (_Float16)(float)exact_f16);  // exact conversions
+}
+
+// Operator preparation for the split-FP16 controlled GEMM: each FP64
+// component w of V, scaled by 2^kOpScaleLog2F16, is split into two FP16
+// pieces (hi = RNE(w'), lo = RNE(w' - hi)); plane p = 2 piece + component,
+// blocked by 16 columns as the BF16 planes.
+__device__ inline void split_value_f16(double2 v, uint16_t* __restrict__ planes, int t, int64_t e) {
+  const int64_t d = int64_t(1) << t;
+  const int64_t dd = d * d;
+  int64_t j = e >> t, c = e & (d - 1);
+  int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
+  double w[2] = {v.x * kOpScaleF16, v.y * kOpScaleF16};
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+    const double hi = f16_round(w[comp]);
+    const double lo = f16_round(w[comp] - hi);
+    planes[(0 * 2 + comp) * dd + dst] = f16_bits(hi);
+    planes[(1 * 2 + comp) * dd + dst] = f16_bits(lo);
+  }
+}
+
 __device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e,
-                                   bool conj = false) {
+                                   bool conj = false, bool f16 = false) {
   double2 v = V[e];
   if (conj) v.y = -v.y;
-  split_value(v, planes, t, e);
+  if (f16)
+    split_value_f16(v, planes, t, e);
+  else
+    split_value(v, planes, t, e);
+}
+
+// The state scale sigma of the split-FP16 products: a power of two with
+// sigma r in [2^13, 2^14), r = ||psi|| 2^(-n/2) the norm of every state row
+// (the H layer gives every row psi 2^(-n/2), and unitary steps keep it), so
+// that no scaled amplitude exceeds 2^14 (FP16 overflows at 65520). One block.
+__device__ inline void state_scale_block(const double2* __restrict__ psi, int n, int t, float* __restrict__ sigma) {
+  __shared__ double red[kThreads];
+  double q = 0.0;
+  for (int i = threadIdx.x; i < (1 << t); i += kThreads) q += psi[i].x * psi[i].x + psi[i].y * psi[i].y;
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(red[0]) * h_scale(n);
+    int e = 0;
+    if (r > 0.0 && r < 1e300) (void)frexp(r, &e);  // r = m 2^e, m in [0.5, 1)
+    const int sh = min(max(kOpScaleLog2F16 - e, -100), 100);
+    *sigma = r > 0.0 && r < 1e300 ? ldexpf(1.0f, sh) : 1.0f;
+  }
 }
 
 __device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
@@ -322,6 +381,7 @@ __global__ void __launch_bounds__(kThreads) k_ns_prep_fused(const double2* __res
 
 // The Newton-Schulz update and the operator split of the new power in one
 // pass: out = X - XE / 2, planes = split(out).
+template <bool F16>
 __global__ void __launch_bounds__(kThreads) k_ns_update_split(const double2* __restrict__ X,
                                                               const float2* __restrict__ XE,
                                                               double2* __restrict__ out,
@@ -332,15 +392,24 @@ __global__ void __launch_bounds__(kThreads) k_ns_update_split(const double2* __r
     const float2 c = XE[e];
     const double2 o = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
     out[e] = o;
-    split_value(o, planes, t, e);
+    if (F16)
+      split_value_f16(o, planes, t, e);
+    else
+      split_value(o, planes, t, e);
   }
 }
 
+template <bool F16>
 __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
                                                            int t) {
   const int64_t dd = int64_t(1) << (2 * t);
   for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
-    split_entry(V, planes, t, e);
+    split_entry(V, planes, t, e, false, F16);
+}
+
+__global__ void __launch_bounds__(kThreads) k_state_scale(const double2* __restrict__ psi, int n, int t,
+                                                          float* __restrict__ sigma) {
+  state_scale_block(psi, n, t, sigma);
 }
 
 __global__ void __launch_bounds__(kThreads) k_sub_identity_defect(double2* __restrict__ G,
@@ -621,10 +690,14 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
     case BK_SPLIT: {
       const double2* V = power_ptr(D, L, power_slot(step, polar));
       uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
+      const bool f16 = (bflags & kBatchF16) != 0;
       int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
-      for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e);
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e, false, f16);
       break;
     }
+    case BK_SCALE:
+      state_scale_block(D.psi, n, t, reinterpret_cast<float*>(defect + kScratchSigma));
+      break;
     case BK_PROB: {
       const int G = d < 64 ? d : 64;
       const int rows_per_wave = 64 / G;
@@ -699,15 +772,26 @@ hipError_t launch_ns_prep_fused(const double2* X, const double2* G, const double
 }
 
 hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* out, uint16_t* planes, int t,
-                                  hipStream_t s) {
+                                  hipStream_t s, bool f16) {
   int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_ns_update_split, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
+  if (f16)
+    hipLaunchKernelGGL(k_ns_update_split<true>, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
+  else
+    hipLaunchKernelGGL(k_ns_update_split<false>, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
   return hipGetLastError();
 }
 
-hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s) {
+hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s, bool f16) {
   int64_t dd = int64_t(1) << (2 * t);
-  hipLaunchKernelGGL(k_split_pieces, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
+  if (f16)
+    hipLaunchKernelGGL(k_split_pieces<true>, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
+  else
+    hipLaunchKernelGGL(k_split_pieces<false>, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_scale(const double2* psi, int n, int t, float* sigma, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_scale, dim3(1), dim3(kThreads), 0, s, psi, n, t, sigma);
   return hipGetLastError();
 }
 

@@ -52,6 +52,14 @@ RunLayout run_layout(int n, int t, int form, unsigned flags) {
   return qpe::run_layout(n, t, form == QPE_FORM_MIXED, !(flags & QPE_NO_POLAR));
 }
 
+// The controlled products of the mixed form run as split-FP16 products
+// (three FP16 products per real one) unless QPE_SPLIT_BF16 asks for the
+// six-product BF16 scheme; the FP16 scaling needs the row norms a unitary U
+// keeps, so without the polar step the BF16 scheme runs.
+bool use_f16(int form, unsigned flags) {
+  return form == QPE_FORM_MIXED && !(flags & QPE_NO_POLAR) && !(flags & QPE_SPLIT_BF16);
+}
+
 int rot_mode(unsigned flags) {
   if (flags & QPE_MIX_TARGET) return kRotForce;
   if (flags & QPE_NO_MIX_TARGET) return kRotOff;
@@ -77,7 +85,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
   BatchPlan P;
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const bool dbl = (flags & QPE_PREFIX_DOUBLING) != 0;
-  tile_flags |= rot_mode(flags) << kBatchRotShift;
+  tile_flags |= (rot_mode(flags) << kBatchRotShift) | (use_f16(form, flags) ? kBatchF16 : 0);
   int32_t table_ints = 0;
   auto add = [&](int kind, int step) {
     int members = 0;
@@ -109,6 +117,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
   add(BK_ROTHASH, 0);
   add(BK_ROTPSI, 0);
   for (int q = 0; q < maxrot; ++q) add(BK_ROTU, q);
+  add(BK_SCALE, 0);
   add(BK_HLAYER, 0);
   add(BK_TWIDDLE, 0);
   for (int k = 0; k < maxn; ++k) {
@@ -174,7 +183,8 @@ qpe_status check_problem(const qpe_problem& p, bool need_ptrs) {
 
 qpe_status check_form_flags(int form, unsigned flags) {
   if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
-  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING | QPE_MIX_TARGET | QPE_NO_MIX_TARGET)) return QPE_ERR_ARG;
+  if (flags & ~unsigned(QPE_NO_POLAR | QPE_PREFIX_DOUBLING | QPE_MIX_TARGET | QPE_NO_MIX_TARGET | QPE_SPLIT_BF16))
+    return QPE_ERR_ARG;
   if ((flags & QPE_MIX_TARGET) && (flags & QPE_NO_MIX_TARGET)) return QPE_ERR_ARG;
   return QPE_OK;
 }
@@ -242,7 +252,7 @@ struct TimerScope {
 // in FP32 into g, which E no longer needs by then.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
                             bool polar, unsigned long long* defect, uint16_t* planes = nullptr,
-                            double2* g2 = nullptr, bool* planes_hold_out = nullptr) {
+                            double2* g2 = nullptr, bool* planes_hold_out = nullptr, bool f16 = false) {
   hipStream_t s = ctx->stream;
   const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
@@ -272,7 +282,7 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
     float2* xe = reinterpret_cast<float2*>(g);
     QPE_HIP(ctx, launch_ns_prep_fused(sq, g, h.C2, x32, planes, tz, defect, s));
     QPE_HIP(ctx, launch_ns_product(x32, xe, planes, tz, s));
-    QPE_HIP(ctx, launch_ns_update_split(sq, xe, out, planes, tz, s));
+    QPE_HIP(ctx, launch_ns_update_split(sq, xe, out, planes, tz, s, f16));
     if (planes_hold_out) *planes_hold_out = true;
     return QPE_OK;
   }
@@ -289,8 +299,10 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   return QPE_OK;
 }
 
+// sigma_f16: device address of the state scale for split-FP16 products, or
+// null for the split-BF16 ones.
 qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const double2* V, void* s0, void* s1,
-                      uint16_t* planes, uint64_t pmask, bool need_split = true) {
+                      uint16_t* planes, uint64_t pmask, bool need_split = true, const float* sigma_f16 = nullptr) {
   hipStream_t s = ctx->stream;
   if (t <= 4) {
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
@@ -298,11 +310,11 @@ qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const doubl
   } else if (mixed) {
     if (need_split) {
       TimerScope ts(ctx, QPE_TIMER_SPLIT);
-      QPE_HIP(ctx, launch_split_pieces(V, planes, t, s));
+      QPE_HIP(ctx, launch_split_pieces(V, planes, t, s, sigma_f16 != nullptr));
     }
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
     QPE_HIP(ctx, launch_ctrl_mixed(static_cast<float2*>(s0), static_cast<float2*>(s1), planes, n, t, k, pmask, s,
-                                    ctx->variant[QPE_KERNEL_CTRL_MIXED][t]));
+                                    ctx->variant[QPE_KERNEL_CTRL_MIXED][t], sigma_f16));
   } else {
     TimerScope ts(ctx, QPE_TIMER_CTRL_GEMM);
     QPE_HIP(ctx, launch_ctrl_f64(static_cast<double2*>(s0), static_cast<double2*>(s1), V, n, t, k, pmask, s,
@@ -375,6 +387,9 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     U0 = Ur;
     psi0 = pr;
   }
+  const bool f16 = use_f16(form, flags) && t >= 5;
+  float* sigma = reinterpret_cast<float*>(defect + kScratchSigma);
+  if (f16) QPE_HIP(ctx, launch_state_scale(psi0, n, t, sigma, s));
   {
     // Prefix doubling writes every row j >= 1 in the step of its top bit,
     // so the H layer only has to fill row 0.
@@ -388,7 +403,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2, &planes_ready);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2, &planes_ready, f16);
       if (st != QPE_OK) return st;
       cur = polar ? other : sq;
     }
@@ -397,9 +412,10 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       // rows [0, 2^k) of s0 -> rows [2^k, 2^(k+1)) of s0: 2^k outputs, as a
       // "register" of k+1 qubits whose second buffer starts at row 2^k.
       char* upper = static_cast<char*>(s0) + (size_t(1) << k) * size_t(d) * amp;
-      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling, !planes_ready);
+      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling, !planes_ready, f16 ? sigma : nullptr);
     } else {
-      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1, !planes_ready);
+      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1, !planes_ready,
+                      f16 ? sigma : nullptr);
     }
     if (st != QPE_OK) return st;
   }
@@ -446,7 +462,8 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
                      qpe_report* report) {
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0) |
-                 batch_variant_flags(ctx) | (rot_mode(flags) << kBatchRotShift);
+                 batch_variant_flags(ctx) | (rot_mode(flags) << kBatchRotShift) |
+                 (use_f16(form, flags) ? kBatchF16 : 0);
   hipStream_t s = ctx->stream;
   const BatchPlan P = plan_batch(p, count, form, flags, true, bf & kBatchGemm64);
   int32_t* tables = reinterpret_cast<int32_t*>(ws);

@@ -104,9 +104,15 @@ __host__ __device__ inline bool gram_split(int t) { return t == 10 || t == 11; }
 
 // The instance's small scratch region holds, as 8-byte words: the unitarity
 // defect (the bits of a non-negative double, atomically maxed), the key of the
-// target rotation, the rotated input's peak weight, and from word
-// kScratchHash on the partial hashes of the rotation key (kRotHashBlocks).
-constexpr int kScratchDefect = 0, kScratchKey = 1, kScratchPeak = 2, kScratchHash = 8;
+// target rotation, the rotated input's peak weight, the state scale sigma of
+// the split-FP16 products (a float in the word's first 4 bytes), and from
+// word kScratchHash on the partial hashes of the rotation key
+// (kRotHashBlocks).
+constexpr int kScratchDefect = 0, kScratchKey = 1, kScratchPeak = 2, kScratchSigma = 3, kScratchHash = 8;
+// Split-FP16 products: the operator is scaled by this power of two before
+// its split (entries of a unitary operator are at most 1 in magnitude).
+constexpr int kOpScaleLog2F16 = 14;
+constexpr double kOpScaleF16 = double(1 << kOpScaleLog2F16);
 constexpr int kRotHashBlocks = 256;
 constexpr int kRotHashChunk = 4096;  // operator elements per hash chunk
 constexpr size_t kScratchBytes = (kScratchHash + kRotHashBlocks) * 8;
@@ -182,6 +188,7 @@ enum BatchKind {
   BK_ROTHASH,  // target rotation: partial hashes of U,
   BK_ROTPSI,   //   the key, M psi and its peak weight,
   BK_ROTU,     //   the Walsh-Hadamard passes of U (step = pass)
+  BK_SCALE,    // state scale of the split-FP16 products
   BK_HLAYER,
   BK_TWIDDLE,
   BK_SQ,
@@ -241,6 +248,8 @@ __host__ __device__ inline int64_t rot_hash_blocks(int t) {
 // controlled step uses the in-step schedule instead of the ping-pong one.
 // Neither changes the order of any sum, so results are the same bit for bit.
 constexpr int kBatchPolar = 1, kBatchDoubling = 2, kBatchGemm64 = 4, kBatchCtrlInStep = 8;
+// kBatchF16: the controlled steps of d >= 32 run as split-FP16 products
+constexpr int kBatchF16 = 64;
 // target rotation mode (RotMode) in bits 4-5
 constexpr int kBatchRotShift = 4;
 __host__ __device__ inline int batch_rot_mode(int bflags) { return (bflags >> kBatchRotShift) & 3; }
@@ -269,6 +278,8 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       const DftPlan pl = rot_plan(t);
       return step < pl.npass ? cdiv(d * d, kWhtTile) : 0;
     }
+    case BK_SCALE:
+      return ((bflags & kBatchF16) && mixed && t >= 5) ? 1 : 0;
     case BK_HLAYER:
       return cdiv(dbl ? d : N * d, kHTile);
     case BK_TWIDDLE: {
@@ -379,7 +390,12 @@ struct BatchLaunch {
 hipError_t launch_h_broadcast(bool mixed, const void* psi, void* state, int n, int t, hipStream_t s,
                               bool first_row_only = false);
 hipError_t launch_twiddles(double2* tw_hi, double2* tw_lo, int n, int h, hipStream_t s);
-hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s);
+// f16: the two FP16 pieces of the split-FP16 products (four planes) instead
+// of the three BF16 pieces (six planes).
+hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s, bool f16 = false);
+// sigma (device float) <- the state scale of the split-FP16 products for
+// input psi and n measurement qubits.
+hipError_t launch_state_scale(const double2* psi, int n, int t, float* sigma, hipStream_t s);
 // Newton-Schulz correction in split BF16 (mixed form): E = G - I and its
 // defect, X32 = complex64(X) and planes = split(conj(E)) in one pass (E itself
 // not stored); after XE = X32 E on the split-BF16 kernel, out = X - XE / 2
@@ -387,7 +403,7 @@ hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStr
 hipError_t launch_ns_prep_fused(const double2* X, const double2* G, const double2* G2, float2* X32, uint16_t* planes,
                                 int t, unsigned long long* defect_bits, hipStream_t s);
 hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* out, uint16_t* planes, int t,
-                                  hipStream_t s);
+                                  hipStream_t s, bool f16 = false);
 // G <- G (+ G2 when not null) - I, and the defect max |G_ij| (atomic max).
 hipError_t launch_sub_identity_defect(double2* G, const double2* G2, int d, unsigned long long* defect_bits,
                                       hipStream_t s);
@@ -460,8 +476,12 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
 int ctrl_f64_variants();
 // Controlled step k, mixed form (d >= 32): split-BF16 operator planes
 // (blocked by 16 columns). variant 0 = default, 1..ctrl_mixed_variants().
+// sigma_f16: null for the split-BF16 products (six pairs of three BF16
+// pieces, operator planes from launch_split_pieces); else the device address
+// of the state scale sigma of the split-FP16 products (three pairs of two
+// FP16 pieces, planes from launch_split_pieces with f16).
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
-                             uint64_t pmask, hipStream_t s, int variant);
+                             uint64_t pmask, hipStream_t s, int variant, const float* sigma_f16 = nullptr);
 int ctrl_mixed_variants();
 // The Newton-Schulz product XE = X32 E (d x d) on the split-BF16 kernel with
 // three piece pairs (E is of the size of the unitarity defect), X32 and the

@@ -26,6 +26,7 @@ NO_POLAR = 1
 PREFIX_DOUBLING = 2
 MIX_TARGET = 4
 NO_MIX_TARGET = 8
+SPLIT_BF16 = 16
 REPORT_NOT_UNITARY = 1
 REPORT_NUMERIC = 2
 REPORT_CONCENTRATED = 4

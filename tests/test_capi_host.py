@@ -77,7 +77,7 @@ def test_size_limits(L, n, t, code):
 def test_bad_form_flags_count(L):
     out = ctypes.c_size_t()
     assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 2, 0, ctypes.byref(out)) == 1
-    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 16, ctypes.byref(out)) == 1
+    assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 32, ctypes.byref(out)) == 1
     # forcing the target rotation on (4) and off (8) at once
     assert L.qpe_workspace_size(_problems([(8, 2)]), 1, 1, 4 | 8, ctypes.byref(out)) == 1
     assert L.qpe_workspace_size(_problems([(8, 2)]), 0, 1, 0, ctypes.byref(out)) == 1
@@ -100,7 +100,8 @@ def test_check_run(L):
     for f in (4, 4 | 1, 8, 8 | 1):
         assert L.qpe_check_run(p, 1, 1, f, ws, need, None) == 0
     assert L.qpe_check_run(p, 1, 1, 4 | 8, ws, need, None) == 1
-    assert L.qpe_check_run(p, 1, 1, 16, ws, need, None) == 1
+    assert L.qpe_check_run(p, 1, 1, 32, ws, need, None) == 1
+    assert L.qpe_check_run(p, 1, 1, 16, ws, need, None) == 0  # QPE_SPLIT_BF16
     two = _problems([(8, 2), (8, 2)])
     for f in (4, 4 | 1):
         # a forced rotation adds launches (table entries) to a batch

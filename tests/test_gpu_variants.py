@@ -33,19 +33,21 @@ def _run_all_variants(qpe, cls, form, n, t, seed, flags=0):
     return p, out
 
 
-@pytest.mark.parametrize("n,t", [(10, 5), (10, 6), (9, 7), (8, 8), (5, 7), (3, 8)])
-def test_ctrl_mixed_variants(qpe, n, t):
-    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 100 + n + t)
+@pytest.mark.parametrize("scheme", [0, 16], ids=["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("n,t", [(10, 5), (10, 6), (9, 7), (8, 8), (5, 7), (3, 8), (12, 7)])
+def test_ctrl_mixed_variants(qpe, n, t, scheme):
+    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 100 + n + t, flags=scheme)
     ref = O.qpe_probs(p.U, p.psi, n)
     for v, P in out.items():
         assert np.array_equal(P, out[0]), f"variant {v} differs from the default"
         assert float(np.abs(P - ref).max()) <= 1e-6, v
 
 
-@pytest.mark.parametrize("n,t", [(9, 7), (6, 8)])
-def test_ctrl_mixed_variants_prefix_doubling(qpe, n, t):
+@pytest.mark.parametrize("scheme", [0, 16], ids=["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("n,t", [(9, 7), (6, 8), (13, 7)])
+def test_ctrl_mixed_variants_prefix_doubling(qpe, n, t, scheme):
     from paper_2507_17175_amd.qpe import PREFIX_DOUBLING
-    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 200 + n + t, flags=PREFIX_DOUBLING)
+    p, out = _run_all_variants(qpe, "ctrl_mixed", "mixed", n, t, 200 + n + t, flags=PREFIX_DOUBLING | scheme)
     ref = O.qpe_probs(p.U, p.psi, n)
     for v, P in out.items():
         assert np.array_equal(P, out[0]), v
