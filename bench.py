@@ -7,15 +7,18 @@ controlled products, inverse QFT, readout) through libqpe's qpe_run, with
 U, psi and the workspace already resident in HBM. Workload (default):
 N_meas = 16, N_mat = 10, a seeded 1024 x 1024 Haar unitary with a uniform
 eigenphase and its eigenvector as input (2^26 amplitudes), in the mixed form
-(complex64 state, split-BF16 matrix-core products with FP32 accumulation,
+(complex64 state, split-FP16 matrix-core products with FP32 accumulation,
 FP64 powers); the plain FP64 form is timed beside it.
 
 Prints one JSON line. `value` = mixed-form circuits/s. `roofline` covers the
 dominant kernel (the controlled-product GEMM): algorithmic flops per launch
 8 * (N/2) * d^2 over its average launch time measured with HIP events on
-the stream it runs on, against the dense BF16 matrix-core peak. The CPU
-baseline is the oracle (numpy/scipy, complex128) on one full circuit of the
-same workload, which also yields the run's max |P_gpu - P_oracle|.
+the stream it runs on, against the dense FP16/BF16 matrix-core peak. Beside
+it: the FP64 form, the prefix-doubling form, the split-BF16 scheme, and
+`batched_c4`, the 512-instance batch (graph-replayed) in the mixed and FP64
+forms. The CPU baseline is the oracle (numpy/scipy, complex128) on one full
+circuit of the same workload, which also yields the run's max
+|P_gpu - P_oracle|.
 """
 from __future__ import annotations
 
@@ -30,12 +33,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_BF16_TFLOPS = 2500.0
+PEAK_F16_TFLOPS = 2500.0  # dense FP16 and BF16 matrix cores
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # "dtype" is the matrix-core type of the dominant kernel; the whole path:
-DTYPE_DETAIL = "split-BF16 x6 products (FP32 accumulate) for the state GEMMs, FP32 QFT, FP64 powers and readout"
+DTYPE_DETAIL = ("split-FP16 x3 products (two FP16 pieces per operand, FP32 accumulate) for the state GEMMs, "
+                "FP32 QFT, FP64 powers, target rotation and readout")
+# executed matrix-core flops per algorithmic flop of each split scheme
+EXECUTED = {"split_fp16x3": 3, "split_bf16x6": 6}
 
 # HBM bytes per launch of the controlled-product kernel at n = 16, t = 10,
 # from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
@@ -47,12 +53,13 @@ TRAFFIC = {
                          "profile": "profiles/ctrl_bf16x6_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
-# variants of the split-BF16 controlled product whose counters TRAFFIC holds
-# at n = 16, t = 10 (0 = the built-in choice there, 7 = the same kernel)
-TRAFFIC_VARIANTS = (0, 7)
-CTRL_KERNELS = {0: "k_ctrl_bf16x6_pp2<128,128>", 1: "k_ctrl_bf16x6<64,64>", 2: "k_ctrl_bf16x6_db<128,128>",
-                3: "k_ctrl_bf16x6_db<128,128> (compiler order)", 4: "k_ctrl_bf16x6_tb<128,128>",
-                5: "k_ctrl_bf16x6_bg<128,128>", 6: "k_ctrl_bf16x6_pp<128,128>", 7: "k_ctrl_bf16x6_pp2<128,128>"}
+# variants of the split-FP16 controlled product that run the kernel whose
+# counters TRAFFIC holds at n = 16, t = 10 (the wide ping-pong kernel: the
+# built-in choice there, variant 8, and the BF16-only designs 3-6, which
+# fall back to it)
+TRAFFIC_VARIANTS = (0, 3, 4, 5, 6, 8)
+CTRL_KERNELS = {1: "k_ctrl_f16x3<128,128>", 2: "k_ctrl_f16x3_db<128,128>", 7: "k_ctrl_f16x3_pp2<128,128>"}
+CTRL_DEFAULT = "k_ctrl_f16x3_pp2<128,256>"
 
 
 def traffic_for_current_kernel():
@@ -139,7 +146,7 @@ def measure_batch(qpe, torch, probs, steps, warmup, autotune=True):
         "max_abs_dP_mixed_vs_fp64": dP,
         "ctrl_gemm": {"algorithmic_flops_per_batch": flops, "ms_per_batch": round(g_ms / steps, 3),
                       "achieved_tflops": round(flops / (g_ms / steps / 1e3) / 1e12, 2),
-                      "frac_of_bf16_peak": round(flops / (g_ms / steps / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                      "frac_of_f16_peak": round(flops / (g_ms / steps / 1e3) / 1e12 / PEAK_F16_TFLOPS, 4),
                       "launches_per_batch": g_cnt // steps},
         "breakdown": {k: {"launches": c // steps, "ms_per_batch": round(ms / steps, 4)}
                       for k, (c, ms) in timing.items()},
@@ -162,7 +169,7 @@ def bench_batch(a, qpe, torch, config_problems):
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": b["ms_per_batch"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
+        "dtype": "fp16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitaries, eigenvector inputs)",
         "config": {"workload": CONFIGS[a.config], "instances": b["instances"], "form": "mixed", "graph": True},
         "batched": b,
@@ -197,14 +204,14 @@ def bench_c5(a, qpe, torch):
         "metric": "QPE circuits/s (mixed form)",
         "value": round(steps / el, 5), "unit": "circuits/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * el / steps, 1), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
+        "vs_baseline": None, "dtype": "fp16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitary generated on the device, eigenvector input)",
         "config": {"workload": CONFIGS["c5"], "n_meas": n, "n_mat": t, "amplitudes": N * d, "form": "mixed",
                    "workspace_bytes": qpe.workspace_bytes([(n, t)], "mixed")},
-        "roofline": {"kernel": "k_ctrl_bf16x6 (controlled product, split-BF16 x6 on MFMA)", "bound": "mfma",
-                     "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                     "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
+        "roofline": {"kernel": "k_ctrl_f16x3 (controlled product, split-FP16 x3 on MFMA)", "bound": "mfma",
+                     "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_F16_TFLOPS, 4),
+                     "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),
                      "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 3),
                      "launches": g_cnt, "traffic": None},
         "breakdown_mixed": {k: {"launches": c, "ms_per_circuit": round(ms / steps, 2)} for k, (c, ms) in timing.items()},
@@ -457,11 +464,11 @@ def main():
     ctx = qpe.context(torch.cuda.current_device())
     ctrl_variant = ctx.get_variant("ctrl_mixed", t) if t >= 5 else None
     roofline = {
-        "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, 'k_ctrl')} (controlled product, split-BF16 x6 on MFMA; "
+        "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, CTRL_DEFAULT)} (controlled product, split-FP16 x3 on MFMA; "
                    f"variant {ctrl_variant})") if t >= 5 else "k_ctrl_small",
-        "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-        "executed_frac": round(6 * achieved / PEAK_BF16_TFLOPS, 4),
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_F16_TFLOPS, 4),
+        "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),
         "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt,
     }
     # traffic: HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE), or null
@@ -483,7 +490,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16", "dtype_detail": DTYPE_DETAIL,
+        "dtype": "fp16", "dtype_detail": DTYPE_DETAIL,
         "data": "synthetic (seeded Haar unitary, eigenvector input)",
         "config": {"workload": CONFIGS[a.config], "n_meas": n, "n_mat": t, "amplitudes": N * d,
                    "state": "complex64", "U": "complex128", "form": "mixed"},
@@ -506,6 +513,20 @@ def main():
         "ctrl_ms_per_circuit": round(dms / a.steps, 4),
         "bitwise_equal_to_gate_route": bool(np.array_equal(P_dbl, P_mixed)),
         "breakdown": {k: {"launches": c, "ms_per_circuit": round(ms / a.steps, 4)} for k, (c, ms) in timing_d.items()},
+    }
+
+    # The six-product split-BF16 scheme (QPE_SPLIT_BF16) on the same
+    # workload, for comparison with the default split-FP16 one.
+    el_b, timing_b, rep_b, P_bf16 = time_form(qpe, torch, prob, "mixed", max(3, a.steps // 2), 1,
+                                               flags=qpe.SPLIT_BF16)
+    bc, bms = timing_b["ctrl_gemm"]
+    bavg = (bms / bc) / 1e3 if bc else float("nan")
+    out["split_bf16_form"] = {
+        "circuits_per_s": round(max(3, a.steps // 2) / el_b, 3),
+        "ctrl_gemm": {"achieved": round(flops_per_launch / bavg / 1e12, 2), "avg_launch_ms": round(bavg * 1e3, 4),
+                      "frac": round(flops_per_launch / bavg / 1e12 / PEAK_F16_TFLOPS, 4),
+                      "executed_frac": round(EXECUTED["split_bf16x6"] * flops_per_launch / bavg / 1e12
+                                             / PEAK_F16_TFLOPS, 4)},
     }
 
     out["end_to_end_mixed"] = end_to_end(qpe, torch, p, "mixed")
@@ -558,6 +579,7 @@ def main():
                                "kind": "oracle", "sample": f"1 full circuit of {CONFIGS[a.config]}",
                                "seconds": round(t1 - t0, 2)}
         out["max_abs_err_mixed"] = float(np.abs(P_mixed - P_ref).max())
+        out["split_bf16_form"]["max_abs_err"] = float(np.abs(P_bf16 - P_ref).max())
         if not a.no_fp64:
             out["fp64_form"]["max_abs_err"] = float(np.abs(P_fp64 - P_ref).max())
     print(json.dumps(out), flush=True)

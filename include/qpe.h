@@ -327,7 +327,9 @@ qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *t
  * choice to every later call. All variants compute the same result up to
  * rounding order. */
 enum {
-  QPE_KERNEL_CTRL_MIXED = 0, /* split-BF16 controlled GEMM (d >= 32)  */
+  QPE_KERNEL_CTRL_MIXED = 0, /* split-FP16 / split-BF16 controlled GEMM
+                                (d >= 32); variant 8 (128 x 256 tiles)
+                                exists for split FP16 only            */
   QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain          */
   QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
   /* Batched runs (count > 1). One setting per context: n_mat is checked
@@ -359,7 +361,7 @@ qpe_status qpe_ctx_get_variant(const qpe_ctx *ctx, int kernel_class, int n_mat, 
  * double[QPE_KERNEL_COUNT * QPE_TUNE_MAX_VARIANTS] or NULL: mean ms per
  * circuit of each (class, variant) tried, -1 where not tried.
  * Errors: as qpe_run; QPE_ERR_ARG for reps out of range or chosen NULL. */
-#define QPE_TUNE_MAX_VARIANTS 8
+#define QPE_TUNE_MAX_VARIANTS 12
 qpe_status qpe_autotune(qpe_ctx *ctx, const qpe_problem *problem, int form, unsigned flags,
                         void *workspace, size_t workspace_bytes, int reps, int *chosen,
                         double *class_ms);

@@ -184,7 +184,9 @@ __device__ __forceinline__ void mma_pair(int c, f32x16 (&acc_re)[FM][FN], f32x16
 // The products of one K chunk of 16 for a scheme: for each kept piece pair,
 // four real products per complex one (re += a.re w.re + a.im (-w.im),
 // im += a.re w.im + a.im w.re), in the order of mma_bf16x6.
-template <class S, int FM, int FN>
+// NEG: negate the imaginary operator fragment next to its use instead of
+// taking it from bneg (shorter register lifetimes for wide tiles).
+template <class S, int FM, int FN, bool NEG = false>
 __device__ __forceinline__ void mma_pair_s(int c, f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
                                            const typename S::v8 (&av)[FM][2 * S::P],
                                            const typename S::v8 (&bv)[FN][2 * S::P],
@@ -201,18 +203,18 @@ __device__ __forceinline__ void mma_pair_s(int c, f32x16 (&acc_re)[FM][FN], f32x
   for (int x = 0; x < FM; ++x)
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
-      acc_re[x][y] = S::mfma(av[x][2 * pa + 1], bneg[y][pb], acc_re[x][y]);
+      acc_re[x][y] = S::mfma(av[x][2 * pa + 1], NEG ? negate(bv[y][2 * pb + 1]) : bneg[y][pb], acc_re[x][y]);
       acc_im[x][y] = S::mfma(av[x][2 * pa + 1], bv[y][2 * pb], acc_im[x][y]);
     }
 }
 
-template <class S, int FM, int FN, int C0 = 0>
+template <class S, int FM, int FN, int C0 = 0, bool NEG = false>
 __device__ __forceinline__ void mma_pieces(f32x16 (&acc_re)[FM][FN], f32x16 (&acc_im)[FM][FN],
                                            const typename S::v8 (&av)[FM][2 * S::P],
                                            const typename S::v8 (&bv)[FN][2 * S::P],
                                            const typename S::v8 (&bneg)[FN][S::P]) {
 #pragma unroll
-  for (int c = C0; c < S::NPAIR; ++c) mma_pair_s<S, FM, FN>(c, acc_re, acc_im, av, bv, bneg);
+  for (int c = C0; c < S::NPAIR; ++c) mma_pair_s<S, FM, FN, NEG>(c, acc_re, acc_im, av, bv, bneg);
 }
 
 // Output layout of the 32x32 MFMA: lane l, element v holds row
@@ -736,16 +738,20 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
         bv[y][pl] = *reinterpret_cast<const V8*>(base + NP * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
     write_b(nb);
     load_b(ns);
+    // wide tiles (two column blocks per wave) negate next to each use
+    constexpr bool kNeg = FN > 1;
+    if constexpr (!kNeg) {
 #pragma unroll
-    for (int y = 0; y < FN; ++y)
+      for (int y = 0; y < FN; ++y)
 #pragma unroll
-      for (int pc2 = 0; pc2 < S::P; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+        for (int pc2 = 0; pc2 < S::P; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
     // matrix phase, with the split and store of the group's rows of slab s+1
     // spread thinly between the MFMAs (one MFMA, then up to three VALU ops)
-    mma_pieces<S, FM, FN>(acc_re, acc_im, av, bv, bneg);
+    mma_pieces<S, FM, FN, 0, kNeg>(acc_re, acc_im, av, bv, bneg);
 #pragma unroll
     for (int u = 0; u < 4; ++u) split_part(u);
     write_a(nb);
@@ -1379,9 +1385,17 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 // Split-FP16 controlled step: the tile choices of the default split-BF16
 // path (variant 1: the 4-wave kernel throughout, 2: the in-step schedule
 // for every size, 7: ping-pong for d >= 128; the BF16-only designs 3-6 fall
-// back to the default).
+// back to the default), and variant 8, the default from d = 256 on: the
+// ping-pong schedule on 128 x 256 tiles (64 x 64 outputs per wave), whose
+// matrix phase holds 48 MFMAs per wave like the split-BF16 kernel's (the
+// 128 x 128 tile gives each phase only 24, and the fixed cost of a phase
+// then weighs twice as much), and which reads the operator planes half as
+// often per row.
 hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                            hipStream_t s, int variant, const float* sigma) {
+  const int64_t wide_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 8 ? (1 << t) / 256 : 0);
+  if (t >= 8 && (variant == 8 || ((variant == 0 || (variant >= 3 && variant <= 6)) && wide_tiles >= 512)))
+    return launch<512>(k_ctrl_f16x3_pp2<128, 256, 2, 4>, 128, 256, buf0, buf1, planes, n, t, k, pmask, s, sigma);
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_f16x3<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
     if (t == 6) return launch<256>(k_ctrl_f16x3<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
@@ -1402,11 +1416,12 @@ hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, i
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 7; }
+int ctrl_mixed_variants() { return 8; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant, const float* sigma_f16) {
   if (sigma_f16) return launch_ctrl_f16(buf0, buf1, planes, n, t, k, pmask, s, variant, sigma_f16);
+  if (variant == 8) variant = 0;  // the wide tile is a split-FP16 kernel
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);

@@ -51,7 +51,7 @@ EXPORTS = (
 STATIC_WORKSPACE_BYTES = 64 << 20
 
 KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2, "batch_ctrl": 3, "batch_gemm": 4}
-TUNE_MAX_VARIANTS = 8
+TUNE_MAX_VARIANTS = 12
 
 TIMERS = {"ctrl_gemm": 0, "powers": 1, "split": 2, "qft": 3, "prob": 4, "hlayer": 5}
 
