@@ -1393,9 +1393,14 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 // often per row.
 hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                            hipStream_t s, int variant, const float* sigma) {
+  // Variants 7 and 8 choose the schedule of launches with enough tiles to
+  // fill the chip (>= 256); smaller ones (early prefix-doubling steps) keep
+  // the default choices.
   const int64_t wide_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 8 ? (1 << t) / 256 : 0);
-  if (t >= 8 && (variant == 8 || ((variant == 0 || (variant >= 3 && variant <= 6)) && wide_tiles >= 512)))
+  if (t >= 8 && ((variant == 8 && wide_tiles >= 256) ||
+                 ((variant == 0 || (variant >= 3 && variant <= 6)) && wide_tiles >= 512)))
     return launch<512>(k_ctrl_f16x3_pp2<128, 256, 2, 4>, 128, 256, buf0, buf1, planes, n, t, k, pmask, s, sigma);
+  if (variant == 8) variant = 0;
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_f16x3<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
     if (t == 6) return launch<256>(k_ctrl_f16x3<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
@@ -1403,7 +1408,7 @@ hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, i
     return hipErrorInvalidValue;
   }
   const int64_t big_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 7 ? (1 << t) / 128 : 1);
-  if (variant != 2 && variant != 7 && t >= 6 && big_tiles < 256)
+  if (variant != 2 && t >= 6 && big_tiles < 256)
     return launch<256>(k_ctrl_f16x3<64, 64, 2, 2>, 64, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
   if (t >= 7 && (variant == 7 || (variant != 2 && big_tiles >= 2048)))
     return launch<512>(k_ctrl_f16x3_pp2<128, 128, 2, 4>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);

@@ -687,6 +687,13 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       }
       break;
     }
+    case BK_PCOPY: {
+      const double2* X = reinterpret_cast<const double2*>(D.ws + L.vbuf);
+      double2* out = reinterpret_cast<double2*>(D.ws + L.tbuf);
+      int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) out[e] = X[e];
+      break;
+    }
     case BK_SPLIT: {
       const double2* V = power_ptr(D, L, power_slot(step, polar));
       uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);

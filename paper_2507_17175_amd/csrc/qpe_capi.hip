@@ -132,6 +132,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
         add(BK_NS_M64, k);
         add(BK_NS_M128, k);
         add(BK_NSUPD, k);
+        add(BK_PCOPY, k);
       }
     }
     if (mixed) {
@@ -402,10 +403,11 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     if (k > 0) {
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
+      const bool pk = polar && ns_step(k);  // this power gets the correction
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, polar, defect, planes, G2, &planes_ready, f16);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes, G2, &planes_ready, f16);
       if (st != QPE_OK) return st;
-      cur = polar ? other : sq;
+      cur = pk ? other : sq;
     }
     qpe_status st;
     if (dbl) {
@@ -439,7 +441,7 @@ int timer_of(int kind) {
     case BK_HLAYER: return QPE_TIMER_HLAYER;
     case BK_ROTHASH: case BK_ROTPSI: case BK_ROTU: return QPE_TIMER_POWERS;
     case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR:
-    case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD:
+    case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD: case BK_PCOPY:
       return QPE_TIMER_POWERS;
     case BK_SPLIT: return QPE_TIMER_SPLIT;
     case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_F64:
@@ -995,7 +997,8 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
   for (int k = 1; k < count_k; ++k) {
     const double2* cur = V + (k - 1) * mat;
     double2* out = V + k * mat;
-    s = square_and_polar(ctx, d, cur, polar ? sq : out, g, out, polar, defect, nullptr, g2);
+    const bool pk = polar && ns_step(k);
+    s = square_and_polar(ctx, d, cur, pk ? sq : out, g, out, pk, defect, nullptr, g2);
     if (s != QPE_OK) return s;
   }
   if (report) {

@@ -166,9 +166,20 @@ __host__ __device__ inline bool rotate_on(bool mixed, int t, int mode, bool pola
   return mode == kRotForce || (mixed && polar && t >= 5);
 }
 
+// The powers that get a Newton-Schulz step (unless QPE_NO_POLAR): the odd
+// k. A squaring doubles the unitarity defect of its operand and adds a
+// rounding of order eps sqrt(d); one Newton-Schulz step brings a defect
+// delta down to about 1.5 delta^2, i.e. to the rounding level. Correcting
+// every second power keeps the defect within a few times that level (the
+// powers at even k carry at most twice the defect of their corrected
+// predecessor) at half the cost of correcting every power.
+__host__ __device__ inline bool ns_step(int k) { return (k & 1) != 0; }
+
 // Where V_k lives during a run: 0 = U itself, 1 = vbuf, 2 = tbuf. With the
-// Newton-Schulz step every square goes to vbuf and the corrected power to
-// tbuf; without it the squares alternate between vbuf (odd k) and tbuf.
+// polar step every square goes to vbuf and V_k to tbuf (the corrected
+// square, or at steps without a correction a copy of it; the single-instance
+// path reads the square where it is); without it the squares alternate
+// between vbuf (odd k) and tbuf.
 __host__ __device__ inline int power_slot(int k, bool polar) {
   if (k == 0) return 0;
   if (polar) return 2;
@@ -200,6 +211,7 @@ enum BatchKind {
   BK_NS_M64,   //   class), update
   BK_NS_M128,
   BK_NSUPD,
+  BK_PCOPY,    // steps without a correction: V_k = the square (vbuf -> tbuf)
   BK_SPLIT,
   BK_CTRL_SMALL,
   BK_CTRL_M32,
@@ -266,6 +278,8 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
   // rows a controlled step writes: the gate route's N/2 rows with bit k set,
   // or the 2^k new rows of the prefix-doubling form
   const int64_t half = dbl ? (step < n ? (int64_t(1) << step) : 0) : N / 2;
+  // power step `step` gets a Newton-Schulz correction
+  const bool ns = polar && step >= 1 && ns_step(step);
   switch (kind) {
     case BK_ZERO:
       return 1;
@@ -293,23 +307,25 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     case BK_GRAM: {
       // Hermitian: the tiles on or above the diagonal (twice when split)
       const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
-      return (polar && step >= 1 && step < n) ? T * (T + 1) / 2 * (gram_split(t) ? 2 : 1) : 0;
+      return (ns && step < n) ? T * (T + 1) / 2 * (gram_split(t) ? 2 : 1) : 0;
     }
     case BK_CORR: {
       const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
-      return (polar && !(mixed && t >= 5) && step >= 1 && step < n) ? T * T : 0;
+      return (ns && !(mixed && t >= 5) && step < n) ? T * T : 0;
     }
     case BK_NSPREP:
     case BK_NSUPD:
-      return (polar && mixed && t >= 5 && step >= 1 && step < n) ? cdiv(d * d, kSplitTile) : 0;
+      return (ns && mixed && t >= 5 && step < n) ? cdiv(d * d, kSplitTile) : 0;
     case BK_NS_M32:
-      return (polar && mixed && t == 5 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 32) : 0;
+      return (ns && mixed && t == 5 && step < n) ? cdiv(d, 128) * (d / 32) : 0;
     case BK_NS_M64:
-      return (polar && mixed && t == 6 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 64) : 0;
+      return (ns && mixed && t == 6 && step < n) ? cdiv(d, 128) * (d / 64) : 0;
     case BK_NS_M128:
-      return (polar && mixed && t >= 7 && step >= 1 && step < n) ? cdiv(d, 128) * (d / 128) : 0;
+      return (ns && mixed && t >= 7 && step < n) ? cdiv(d, 128) * (d / 128) : 0;
     case BK_SUBI:
-      return (polar && step >= 1 && step < n) ? cdiv(d * d, kSubiTile) : 0;
+      return (ns && step < n) ? cdiv(d * d, kSubiTile) : 0;
+    case BK_PCOPY:
+      return (polar && step >= 1 && !ns_step(step) && step < n) ? cdiv(d * d, kSplitTile) : 0;
     case BK_SPLIT:
       return (mixed && t >= 5 && step < n) ? cdiv(d * d, kSplitTile) : 0;
     case BK_CTRL_SMALL:
