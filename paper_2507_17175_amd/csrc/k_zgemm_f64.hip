@@ -10,9 +10,11 @@
 // Tiling: 256 or 512 threads = 4 or 8 wave64s in a WM x WN grid; the
 // workgroup tile is BM x BN complex outputs, the K loop steps by BK = 16
 // complex. Operands are staged in LDS as [k][i] / [k][j] (i or j
-// contiguous, one double2 of padding per row) in two buffers: the next K
-// slab is loaded into registers while the current one feeds the MFMAs, then
-// stored into the other buffer, with one barrier per slab. The 1-D grid is remapped so that each of
+// contiguous, one double2 of padding per row), and the next K slab is
+// prefetched into registers while the current one feeds the MFMAs. (A
+// second LDS buffer, one barrier per slab instead of two, measured 2-4 %
+// slower on every shape here: twice the LDS per workgroup leaves fewer
+// workgroups per CU to cover the barriers.) The 1-D grid is remapped so that each of
 // the 8 XCDs (which own separate L2 caches) walks a contiguous range of
 // tiles, keeping the tiles of one row block on one XCD.
 #include "qpe_internal.hpp"
@@ -58,8 +60,8 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
   static_assert(LA * kThreads == BM * kBK && LB * kThreads == BN * kBK, "tile/thread mismatch");
   constexpr int PA = BM + 1, PB = BN + 1;    // padded LDS row length
 
-  __shared__ double2 As[2][kBK * PA];
-  __shared__ double2 Bs[2][kBK * PB];
+  __shared__ double2 As[kBK * PA];
+  __shared__ double2 Bs[kBK * PB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i0 = tile_m * BM, j0 = tile_n * BN;
@@ -100,7 +102,7 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
       ra[q] = ok ? v : make_double2(0.0, 0.0);
     }
   };
-  auto store_a = [&](int b) {
+  auto store_a = [&]() {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       int idx = tid + q * kThreads;
@@ -112,7 +114,7 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
         kk = idx / BM;
         r = idx % BM;
       }
-      As[b][kk * PA + r] = ra[q];
+      As[kk * PA + r] = ra[q];
     }
   };
   auto load_b = [&](int k0) {
@@ -140,7 +142,7 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
       rb[q] = ok ? v : make_double2(0.0, 0.0);
     }
   };
-  auto store_b = [&](int b) {
+  auto store_b = [&]() {
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
       int idx = tid + q * kThreads;
@@ -152,7 +154,7 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
         c = idx / kBK;
         kk = idx % kBK;
       }
-      Bs[b][kk * PB + c] = rb[q];
+      Bs[kk * PB + c] = rb[q];
     }
   };
 
@@ -173,13 +175,12 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
   const int nk = (a.K + kBK - 1) / kBK;
   load_a(0);
   load_b(0);
-  store_a(0);
-  store_b(0);
+  store_a();
+  store_b();
   __syncthreads();
 
   const int lr = lane & 15, lk = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cb = kt & 1;
     if (kt + 1 < nk) {
       load_a((kt + 1) * kBK);
       load_b((kt + 1) * kBK);
@@ -191,12 +192,12 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
       double as[FM], bs[FN];
 #pragma unroll
       for (int x = 0; x < FM; ++x) {
-        av[x] = As[cb][kr * PA + wi0 + x * 16 + lr];
+        av[x] = As[kr * PA + wi0 + x * 16 + lr];
         as[x] = av[x].x + av[x].y;
       }
 #pragma unroll
       for (int y = 0; y < FN; ++y) {
-        bv[y] = Bs[cb][kr * PB + wj0 + y * 16 + lr];
+        bv[y] = Bs[kr * PB + wj0 + y * 16 + lr];
         bs[y] = bv[y].x + bv[y].y;
       }
 #pragma unroll
@@ -208,13 +209,12 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
           acc_t3[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[x], bs[y], acc_t3[x][y], 0, 0, 0);
         }
     }
-    // the other buffer was last read in slab kt - 1, before the barrier
-    // that ended it; it is read again after the barrier below
-    if (kt + 1 < nk) {
-      store_a(cb ^ 1);
-      store_b(cb ^ 1);
-    }
     __syncthreads();
+    if (kt + 1 < nk) {
+      store_a();
+      store_b();
+      __syncthreads();
+    }
   }
 
   // Epilogue. Output layout of the 16x16 f64 MFMA: lane l, element v holds
