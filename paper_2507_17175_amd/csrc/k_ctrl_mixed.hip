@@ -1332,7 +1332,11 @@ __global__ void __launch_bounds__(KIND == BK_CTRL_M32 || KIND == BK_NS_M32 ? 256
 kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __restrict__ table, int bflags,
               int64_t tile0) {
   constexpr bool NS = KIND == BK_NS_M32 || KIND == BK_NS_M64 || KIND == BK_NS_M128;
-  constexpr int BN = (KIND == BK_CTRL_M32 || KIND == BK_NS_M32) ? 32 : ((KIND == BK_CTRL_M64 || KIND == BK_NS_M64) ? 64 : 128);
+  constexpr int BN = (KIND == BK_CTRL_M32 || KIND == BK_NS_M32)   ? 32
+                     : (KIND == BK_CTRL_M64 || KIND == BK_NS_M64) ? 64
+                     : KIND == BK_CTRL_M256                       ? 256
+                                                                  : 128;
+  static_assert(KIND != BK_CTRL_M256 || F16, "128 x 256 tiles exist for split FP16 only");
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
   const InstDesc D = desc[i];
@@ -1367,6 +1371,8 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
     ctrl_v1_tile<S, 128, 32, 4, 1, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else if constexpr (BN == 64)
     ctrl_db_tile<S, 128, 64, 4, 2, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
+  else if constexpr (BN == 256)
+    ctrl_pp2_tile<S, 128, 256, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else if constexpr (NS || INSTEP)
     ctrl_db_tile<S, 128, 128, 2, 4, true, C0>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
   else
@@ -1526,6 +1532,11 @@ hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, con
         return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
           hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M128, false, true>), dim3(g), dim3(512), 0, s, step, desc, table, p,
                              b);
+        });
+      case BK_CTRL_M256:
+        return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+          hipLaunchKernelGGL((kb_ctrl_mixed<BK_CTRL_M256, false, true>), dim3(g), dim3(512), 0, s, step, desc, table,
+                             p, b);
         });
       default:
         break;  // the Newton-Schulz kinds run in split BF16

@@ -141,6 +141,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
       add(BK_CTRL_M32, k);
       add(BK_CTRL_M64, k);
       add(BK_CTRL_M128, k);
+      add(BK_CTRL_M256, k);
     } else {
       add(BK_CTRL_SMALL, k);
       add(BK_CTRL_F64, k);
@@ -444,7 +445,8 @@ int timer_of(int kind) {
     case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD: case BK_PCOPY:
       return QPE_TIMER_POWERS;
     case BK_SPLIT: return QPE_TIMER_SPLIT;
-    case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_F64:
+    case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_M256:
+    case BK_CTRL_F64:
       return QPE_TIMER_CTRL_GEMM;
     case BK_QFT: return QPE_TIMER_QFT;
     case BK_PROB: case BK_REPORT: return QPE_TIMER_PROB;
@@ -518,6 +520,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_CTRL_M32:
       case BK_CTRL_M64:
       case BK_CTRL_M128:
+      case BK_CTRL_M256:
       case BK_NS_M32:
       case BK_NS_M64:
       case BK_NS_M128:

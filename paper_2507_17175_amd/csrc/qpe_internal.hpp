@@ -217,6 +217,7 @@ enum BatchKind {
   BK_CTRL_M32,
   BK_CTRL_M64,
   BK_CTRL_M128,
+  BK_CTRL_M256,  // split FP16, d >= 256: 128 x 256 tiles
   BK_CTRL_F64,
   BK_QFT,
   BK_PROB,
@@ -335,7 +336,9 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     case BK_CTRL_M64:
       return (mixed && t == 6 && step < n) ? cdiv(half, 128) * (d / 64) : 0;
     case BK_CTRL_M128:
-      return (mixed && t >= 7 && step < n) ? cdiv(half, 128) * (d / 128) : 0;
+      return (mixed && (t == 7 || (t >= 8 && !(bflags & kBatchF16))) && step < n) ? cdiv(half, 128) * (d / 128) : 0;
+    case BK_CTRL_M256:
+      return (mixed && t >= 8 && (bflags & kBatchF16) && step < n) ? cdiv(half, 128) * (d / 256) : 0;
     case BK_CTRL_F64:
       return (!mixed && t >= 5 && step < n) ? cdiv(half, 64) * cdiv(d, 64) : 0;
     case BK_QFT: {
