@@ -157,6 +157,10 @@ typedef struct qpe_ctx qpe_ctx;
 
 /* Create a context bound to HIP device `device` and HIP stream `stream`
  * (a hipStream_t; NULL = the legacy default stream). Host memory only.
+ * For tests of the error path: if the environment variable QPE_FAULT_INJECT
+ * holds a number N >= 1 when the context is created, the N-th checked HIP
+ * call made for it is not made and is reported as failed (QPE_ERR_HIP,
+ * qpe_last_error says so); later calls run normally.
  * Errors: QPE_ERR_ARG (ctx NULL), QPE_ERR_NO_DEVICE, QPE_ERR_OOM. */
 qpe_status qpe_ctx_create(qpe_ctx **ctx, int device, void *stream);
 

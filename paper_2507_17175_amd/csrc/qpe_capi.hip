@@ -40,6 +40,12 @@ struct qpe_ctx {
   unsigned timer_mask = (1u << QPE_TIMER_COUNT) - 1;  // timer classes that record events
   // kernel variant per class (0 = default)
   int variant[QPE_KERNEL_COUNT][QPE_MAX_N_MAT + 1] = {};
+  // fault injection for tests of the error path: the checked HIP call with
+  // this ordinal (counting from 1 on this context) is reported as failed
+  // without being made; 0 = off (environment variable QPE_FAULT_INJECT at
+  // creation)
+  long fault_at = 0;
+  long hip_calls = 0;
 };
 
 namespace {
@@ -220,6 +226,9 @@ qpe_status hip_fail(qpe_ctx* ctx, hipError_t e, const char* what) {
   return QPE_ERR_HIP;
 }
 
+// True when this checked HIP call is the one QPE_FAULT_INJECT names.
+bool injected_fault(qpe_ctx* ctx) { return ctx->fault_at > 0 && ++ctx->hip_calls == ctx->fault_at; }
+
 // Brackets the launches made inside its scope with a pair of events on the
 // context stream when timing is enabled and the pool has room.
 struct TimerScope {
@@ -237,10 +246,11 @@ struct TimerScope {
   }
 };
 
-#define QPE_HIP(ctx, expr)                               \
-  do {                                                   \
-    hipError_t e_ = (expr);                              \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+#define QPE_HIP(ctx, expr)                                                              \
+  do {                                                                                  \
+    const bool inj_ = injected_fault(ctx);                                              \
+    hipError_t e_ = inj_ ? hipErrorLaunchFailure : (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, inj_ ? "injected fault (QPE_FAULT_INJECT): " #expr : #expr); \
   } while (0)
 
 // V_next = cur^2, then (unless no_polar) one Newton-Schulz step
@@ -627,6 +637,7 @@ QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
   if (!c) return QPE_ERR_OOM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  if (const char* f = std::getenv("QPE_FAULT_INJECT")) c->fault_at = std::strtol(f, nullptr, 10);
   {
     // set-up of the static workspace on this device (its failure only
     // affects qpe_run_static, which then reports it)

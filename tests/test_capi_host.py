@@ -185,3 +185,22 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
             qpe.load_library(str(tmp_path / "missing.so"))
         finally:
             qpe._lib = qpe._lib_saved
+
+
+@pytest.mark.slow
+def test_host_code_under_sanitizers():
+    """Every host-side entry point (argument, size, alignment and workspace
+    checks, single and batched workspace planning up to 4500 uneven
+    instances, stage-entry sizes, null contexts, status strings) driven from
+    plain C against a build whose host code carries AddressSanitizer and
+    UndefinedBehaviorSanitizer: no finding, every expectation holds."""
+    import subprocess as sp
+
+    from tests import host_sanitize as H
+    r = H.run()
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "HOST CHECKS OK" in r.stdout
+    assert "AddressSanitizer" not in out and "runtime error" not in out
+    syms = sp.run(["nm", "-D", H.LIB], capture_output=True, text=True).stdout
+    assert "__asan_" in syms and "__ubsan_handle" in syms  # the sanitizers are really in
