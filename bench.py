@@ -49,8 +49,8 @@ EXECUTED = {"split_fp16x3": 3, "split_bf16x6": 6}
 # SHA-256 of the kernel source the counters were taken on. A changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    "6c4a1f173bcc5eca": {"fetch_bytes": 524376.0 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
-                         "profile": "profiles/ctrl_bf16x6_qpe_n16_t10_hbm.md"},
+    "e24b635f4d76b6ff": {"fetch_bytes": 262249.3 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
+                         "profile": "profiles/ctrl_f16x3_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
 # variants of the split-FP16 controlled product that run the kernel whose
@@ -208,7 +208,7 @@ def bench_c5(a, qpe, torch):
         "data": "synthetic (seeded Haar unitary generated on the device, eigenvector input)",
         "config": {"workload": CONFIGS["c5"], "n_meas": n, "n_mat": t, "amplitudes": N * d, "form": "mixed",
                    "workspace_bytes": qpe.workspace_bytes([(n, t)], "mixed")},
-        "roofline": {"kernel": "k_ctrl_f16x3 (controlled product, split-FP16 x3 on MFMA)", "bound": "mfma",
+        "roofline": {"kernel": CTRL_DEFAULT + " (controlled product, split-FP16 x3 on MFMA)", "bound": "mfma",
                      "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_F16_TFLOPS, 4),
                      "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),

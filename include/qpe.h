@@ -140,7 +140,8 @@ typedef struct qpe_problem {
 
 /* Device-written diagnostics, one per instance (caller-owned device memory,
  * 8-byte aligned). unitarity_defect is the largest max-norm of V^H V - I met
- * before each Newton-Schulz step (the powers of odd k; 0 when QPE_NO_POLAR); prob_sum = sum_m P(m);
+ * before each Newton-Schulz step (the powers k = 3, 7, 11, ... and the last
+ * one, k = n_meas - 1; 0 when QPE_NO_POLAR); prob_sum = sum_m P(m);
  * psi_norm2 = ||psi||^2; input_peak = max_i |x_i|^2 / ||psi||^2 for the input
  * x of the state path (M psi when the target register was rotated, else
  * psi). */
@@ -229,11 +230,12 @@ qpe_status qpe_check_run(const qpe_problem *problems, int count, int form, unsig
 /* ---- stage entry points (one step of the path each, for per-step checks) ---- */
 
 /* Powers of U (the controlled operators of Fig. 1): V_k = U^(2^k) for
- * k = 0 .. count_k-1, by FP64 repeated squaring; the squares of odd k are
- * followed by one Newton-Schulz step X <- X (3I - X^H X)/2 unless
- * QPE_NO_POLAR (a squaring doubles the unitarity defect, one step takes a
- * defect delta to about 1.5 delta^2, so correcting every second power keeps
- * it near the rounding level; qpe_run uses the same schedule).
+ * k = 0 .. count_k-1, by FP64 repeated squaring; the squares of k = 3, 7,
+ * 11, ... and of the last k (count_k - 1) are followed by one Newton-Schulz
+ * step X <- X (3I - X^H X)/2 unless QPE_NO_POLAR (a squaring doubles the
+ * unitarity defect, one step takes a defect delta to about 1.5 delta^2, so
+ * correcting every fourth power keeps it within about eight times the
+ * rounding level; qpe_run uses the same schedule with count_k = n_meas).
  * U: device complex128 [d*d]; V_out: device complex128 [count_k][d][d];
  * workspace: >= qpe_powers_workspace_size bytes; report: device qpe_report
  * or NULL (only unitarity_defect is written). 1 <= count_k <= 30. */

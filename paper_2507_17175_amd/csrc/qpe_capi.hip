@@ -389,8 +389,8 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   const bool rot = rotate_on(mixed, t, rot_mode(flags), polar);
   if (rot) {
     // U' goes to A: it is read as V_0 by step 0 and by the first square,
-    // which writes B; A is next written by the power step of k = 1 (polar)
-    // or k = 2. M psi goes to the second state buffer, read by the H layer
+    // which writes B; A is next written by the power step of k = 1 (when
+    // it gets a Newton-Schulz step) or k = 2. M psi goes to the second state buffer, read by the H layer
     // before step 0 writes there (the prefix-doubling form never does).
     double2* Ur = A;
     double2* pr = static_cast<double2*>(s1);
@@ -414,7 +414,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     if (k > 0) {
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
-      const bool pk = polar && ns_step(k);  // this power gets the correction
+      const bool pk = polar && ns_step(k, n);  // this power gets the correction
       TimerScope ts(ctx, QPE_TIMER_POWERS);
       qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes, G2, &planes_ready, f16);
       if (st != QPE_OK) return st;
@@ -1011,7 +1011,7 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
   for (int k = 1; k < count_k; ++k) {
     const double2* cur = V + (k - 1) * mat;
     double2* out = V + k * mat;
-    const bool pk = polar && ns_step(k);
+    const bool pk = polar && ns_step(k, count_k);
     s = square_and_polar(ctx, d, cur, pk ? sq : out, g, out, pk, defect, nullptr, g2);
     if (s != QPE_OK) return s;
   }

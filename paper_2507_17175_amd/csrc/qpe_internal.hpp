@@ -166,14 +166,17 @@ __host__ __device__ inline bool rotate_on(bool mixed, int t, int mode, bool pola
   return mode == kRotForce || (mixed && polar && t >= 5);
 }
 
-// The powers that get a Newton-Schulz step (unless QPE_NO_POLAR): the odd
-// k. A squaring doubles the unitarity defect of its operand and adds a
-// rounding of order eps sqrt(d); one Newton-Schulz step brings a defect
-// delta down to about 1.5 delta^2, i.e. to the rounding level. Correcting
-// every second power keeps the defect within a few times that level (the
-// powers at even k carry at most twice the defect of their corrected
-// predecessor) at half the cost of correcting every power.
-__host__ __device__ inline bool ns_step(int k) { return (k & 1) != 0; }
+// The powers that get a Newton-Schulz step (unless QPE_NO_POLAR), in a run
+// whose powers are V_0 .. V_{n-1}: every fourth one (k = 3, 7, 11, ...) and
+// the last. A squaring doubles the unitarity defect of its operand and adds
+// a rounding of order eps sqrt(d); one Newton-Schulz step brings a defect
+// delta down to about 1.5 delta^2, i.e. to the rounding level. Between two
+// corrections the defect therefore grows at most about eightfold from that
+// level (about 1e-15 at d = 512..1024), far inside what the probabilities
+// notice, at a quarter of the cost of correcting every power. Correcting the
+// last power means that every run with n >= 2 measures the defect of the
+// operators it applies last.
+__host__ __device__ inline bool ns_step(int k, int n) { return k >= 1 && ((k & 3) == 3 || k == n - 1); }
 
 // Where V_k lives during a run: 0 = U itself, 1 = vbuf, 2 = tbuf. With the
 // polar step every square goes to vbuf and V_k to tbuf (the corrected
@@ -280,7 +283,7 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
   // or the 2^k new rows of the prefix-doubling form
   const int64_t half = dbl ? (step < n ? (int64_t(1) << step) : 0) : N / 2;
   // power step `step` gets a Newton-Schulz correction
-  const bool ns = polar && step >= 1 && ns_step(step);
+  const bool ns = polar && step >= 1 && ns_step(step, n);
   switch (kind) {
     case BK_ZERO:
       return 1;
@@ -326,7 +329,7 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
     case BK_SUBI:
       return (ns && step < n) ? cdiv(d * d, kSubiTile) : 0;
     case BK_PCOPY:
-      return (polar && step >= 1 && !ns_step(step) && step < n) ? cdiv(d * d, kSplitTile) : 0;
+      return (polar && step >= 1 && !ns_step(step, n) && step < n) ? cdiv(d * d, kSplitTile) : 0;
     case BK_SPLIT:
       return (mixed && t >= 5 && step < n) ? cdiv(d * d, kSplitTile) : 0;
     case BK_CTRL_SMALL:
