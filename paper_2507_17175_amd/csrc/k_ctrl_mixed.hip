@@ -712,9 +712,13 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
   for (int u = 0; u < 4; ++u) split_part(u);
   write_a(0);
   write_b(0);
+  // Slab 1 is loaded in the loop's order (operator chunks, then state rows):
+  // the compiler's wait counts at the loop head cover both ways in, so with
+  // the prologue's order reversed the memory phase would also wait for the
+  // state rows loaded at the end of the previous matrix phase.
   if (nk > 1) {
-    load_a(1);
     load_b(1);
+    load_a(1);
   }
   __syncthreads();
   if (grp == 1) __syncthreads();
@@ -1339,7 +1343,7 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
   static_assert(KIND != BK_CTRL_M256 || F16, "128 x 256 tiles exist for split FP16 only");
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const bool dbl = NS || (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, true, (bflags & kBatchPolar) != 0);
   const uint16_t* planes = reinterpret_cast<const uint16_t*>(D.ws + L.planes);

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDe
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed, pol);
   const int slot = power_slot(step, pol);

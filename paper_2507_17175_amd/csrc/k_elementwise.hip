@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
   constexpr bool mixed = sizeof(T) == 8;
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const RunLayout L = run_layout(D.n, D.t, mixed, polar);
   const int n = D.n, t = D.t, d = 1 << t;
   const int64_t N = int64_t(1) << n;

@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __r
   __shared__ T L[WIDE ? 2 * kQftLds : kQftLds];
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const RunLayout lay = run_layout(D.n, D.t, mixed, (bflags & kBatchPolar) != 0);
   const DftPlan plan = make_dft_plan(D.n);
   int before = 0;

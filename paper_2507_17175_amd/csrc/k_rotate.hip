@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(kThreads) kb_rotate(int step, const InstDesc* 
                                                       int64_t tile0) {
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const RunLayout L = run_layout(D.n, D.t, mixed != 0, (bflags & kBatchPolar) != 0);
   unsigned long long* scratch = reinterpret_cast<unsigned long long*>(D.ws + L.scratch);
   const int t = D.t;

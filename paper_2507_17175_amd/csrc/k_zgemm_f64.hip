@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
   constexpr int OPA = KIND == BK_GRAM ? OP_C : OP_N;
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const bool pol = (bflags & kBatchPolar) != 0;
   const RunLayout L = run_layout(D.n, D.t, mixed != 0, pol);
   const int d = 1 << D.t;
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __r
                                                    const int32_t* __restrict__ table, int bflags, int64_t tile0) {
   int64_t local;
   const int i = find_member(table, tile0 + blockIdx.x, &local);
-  const InstDesc D = desc[i];
+  const InstDesc D = load_desc(desc, i);
   const bool pol = (bflags & kBatchPolar) != 0, dbl = (bflags & kBatchDoubling) != 0;
   const RunLayout L = run_layout(D.n, D.t, false, pol);
   const int d = 1 << D.t;

@@ -247,6 +247,42 @@ struct InstDesc {
   char* ws;        // this instance's region of the workspace
 };
 
+// The same record as the grouped kernels read it: every pointer in it
+// addresses device global memory. Read through plain pointers, whose address
+// space the compiler cannot see, the instance's buffers would be accessed
+// with flat instructions, and a flat load counts in the LDS wait counter too:
+// each wait for LDS data (before every workgroup barrier of the tiled
+// kernels) would then also wait for all global loads still in flight.
+#define QPE_GLOBAL __attribute__((address_space(1)))
+struct InstDescGlobal {
+  int32_t n, t;
+  const QPE_GLOBAL double2* U;
+  const QPE_GLOBAL double2* psi;
+  const QPE_GLOBAL double2* U_src;
+  const QPE_GLOBAL double2* psi_src;
+  QPE_GLOBAL double* prob;
+  QPE_GLOBAL double* report;
+  QPE_GLOBAL char* ws;
+};
+static_assert(sizeof(InstDescGlobal) == sizeof(InstDesc) && offsetof(InstDescGlobal, ws) == offsetof(InstDesc, ws),
+              "one layout");
+
+// Descriptor i, with pointers the compiler knows to be global.
+__device__ __forceinline__ InstDesc load_desc(const InstDesc* desc, int i) {
+  const InstDescGlobal g = reinterpret_cast<const InstDescGlobal*>(desc)[i];
+  InstDesc D;
+  D.n = g.n;
+  D.t = g.t;
+  D.U = (const double2*)g.U;
+  D.psi = (const double2*)g.psi;
+  D.U_src = (const double2*)g.U_src;
+  D.psi_src = (const double2*)g.psi_src;
+  D.prob = (double*)g.prob;
+  D.report = (double*)g.report;
+  D.ws = (char*)g.ws;
+  return D;
+}
+
 // Passes of the Walsh-Hadamard transform over the 2t bits of a flattened
 // d x d operator (balanced passes of at most 8 bits, as the DFT plan).
 __host__ __device__ inline DftPlan rot_plan(int t) { return make_dft_plan(2 * t); }
