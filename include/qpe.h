@@ -347,7 +347,17 @@ enum {
                                 1 in-step schedule, 2 ping-pong (default) */
   QPE_KERNEL_BATCH_GEMM = 4, /* grouped FP64 power-chain products: 1 32x32
                                 tiles (default), 2 64x64 tiles for d >= 64 */
-  QPE_KERNEL_COUNT = 5
+  QPE_KERNEL_BATCH_SCHED = 5, /* schedule of a batched run with the polar
+                                 step: 1 one stream, 2 (default) the power
+                                 chain on a second stream of the context
+                                 (created, with its events, on first use), so
+                                 that the squares and Gram products of step
+                                 k+1 overlap the controlled products of step
+                                 k; joined back into the context stream before
+                                 the run returns, also when it fails. With
+                                 per-kernel timing on, or in qpe_run_static
+                                 (which creates nothing), one stream. */
+  QPE_KERNEL_COUNT = 6
 };
 qpe_status qpe_kernel_variants(int kernel_class, int *count);
 /* n_mat selects the operator size the choice applies to (0..QPE_MAX_N_MAT),
@@ -376,9 +386,10 @@ qpe_status qpe_autotune(qpe_ctx *ctx, const qpe_problem *problem, int form, unsi
                         double *class_ms);
 
 /* The same for a batched run (the grouped kernels of `count` >= 2 problems):
- * each batched class this batch uses (QPE_KERNEL_BATCH_GEMM when any
- * instance has n_meas >= 2, QPE_KERNEL_BATCH_CTRL in the mixed form when
- * any instance has n_mat >= 7) is timed over whole batched runs, every
+ * each batched class this batch uses (QPE_KERNEL_BATCH_GEMM and, with the
+ * polar step, QPE_KERNEL_BATCH_SCHED when any instance has n_meas >= 2,
+ * QPE_KERNEL_BATCH_CTRL in the mixed form when any instance has
+ * n_mat >= 7) is timed over whole batched runs, every
  * variant in turn, and the fastest is kept. Arguments, outputs and errors
  * as qpe_autotune, with the problems, count and workspace of qpe_run;
  * every problem's prob vector is overwritten. */

@@ -46,6 +46,10 @@ struct qpe_ctx {
   // creation)
   long fault_at = 0;
   long hip_calls = 0;
+  // second stream and events of the two-stream batch schedule (created on
+  // first use, default priority)
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> sched_ev;
 };
 
 namespace {
@@ -472,8 +476,42 @@ int batch_variant_flags(const qpe_ctx* ctx) {
   return f;
 }
 
+// Launch kinds of power step k that only read V_{k-1} and write the
+// instance's square and Gram buffers, which no state-side launch touches:
+// they may run while the controlled products of step k-1 still read V_{k-1}
+// and the operator planes.
+bool chain_ahead(int kind) { return kind == BK_SQ || kind == BK_GRAM || kind == BK_SUBI; }
+// The rest of power step k: they write V_k's slot, the planes (the mixed
+// Newton-Schulz product stages conj(E) there) or the staging in it, so they
+// wait for the controlled products of step k-1.
+bool chain_after(int kind) {
+  return kind == BK_CORR || kind == BK_NSPREP || kind == BK_NS_M32 || kind == BK_NS_M64 || kind == BK_NS_M128 ||
+         kind == BK_NSUPD || kind == BK_PCOPY;
+}
+// State-side launches of controlled step k.
+bool state_step(int kind) {
+  return kind == BK_SPLIT || kind == BK_CTRL_SMALL || kind == BK_CTRL_M32 || kind == BK_CTRL_M64 ||
+         kind == BK_CTRL_M128 || kind == BK_CTRL_M256 || kind == BK_CTRL_F64;
+}
+// Events of one run of the two-stream schedule: at most two hops per step
+// plus the fork and the join, so no event is recorded twice in one run.
+constexpr int kSchedEvents = 2 * QPE_MAX_N_MEAS + 4;
+
+// The second stream and `nev` events of the two-stream schedule.
+qpe_status ensure_sched(qpe_ctx* ctx, int nev) {
+  if (!ctx->aux) QPE_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  while (int(ctx->sched_ev.size()) < nev) {
+    hipEvent_t e = nullptr;
+    QPE_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->sched_ev.push_back(e);
+  }
+  return QPE_OK;
+}
+
+// allow_aux: the two-stream schedule may be used (it creates the second
+// stream and its events on first use).
 qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, unsigned flags, char* ws,
-                     qpe_report* report) {
+                     qpe_report* report, bool allow_aux = true) {
   const bool mixed = form == QPE_FORM_MIXED, polar = !(flags & QPE_NO_POLAR);
   const int bf = (polar ? kBatchPolar : 0) | ((flags & QPE_PREFIX_DOUBLING) ? kBatchDoubling : 0) |
                  batch_variant_flags(ctx) | (rot_mode(flags) << kBatchRotShift) |
@@ -513,10 +551,55 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
     int c = nl - first < kBatchLaunchChunk ? nl - first : kBatchLaunchChunk;
     QPE_HIP(ctx, launch_batch_tables(desc, count, tables, P.launches.data() + first, c, mixed, bf, s));
   }
+  // Two-stream schedule: the power chain goes to ctx->aux. Step k's first
+  // state-side launch waits for the chain through step k; the second part
+  // of power step k waits for the state side through step k-1 (the plan
+  // lists, for each k, the chain's launches before the state's). Per-kernel
+  // timers bracket launches on the context stream, so timing keeps one.
+  const bool pipe = allow_aux && polar && ctx->variant[QPE_KERNEL_BATCH_SCHED][0] != 1 && !ctx->timing;
+  int next_ev = 0;
+  bool forked = false, aux_pending = false;
+  int ctrl_waited = -1;  // the last step whose state-side launches the chain waited for
+  hipStream_t s_state = s;
+  auto hop = [&](hipStream_t from, hipStream_t to) -> qpe_status {
+    // `to` waits for everything enqueued on `from` so far
+    hipEvent_t e = ctx->sched_ev[size_t(next_ev++) % ctx->sched_ev.size()];
+    QPE_HIP(ctx, hipEventRecord(e, from));
+    QPE_HIP(ctx, hipStreamWaitEvent(to, e, 0));
+    return QPE_OK;
+  };
+  if (pipe) {
+    qpe_status st = ensure_sched(ctx, kSchedEvents);
+    if (st != QPE_OK) return st;
+  }
+  qpe_status result = [&]() -> qpe_status {
   for (int l = 0; l < nl; ++l) {
     const BatchLaunch& L = P.launches[l];
     const int32_t* tab = tables + L.table_off;
     const int64_t tiles = P.tiles[l];
+    s = s_state;
+    if (pipe) {
+      const bool ahead = chain_ahead(L.kind), after = chain_after(L.kind);
+      qpe_status st = QPE_OK;
+      if (!forked && (ahead || after || state_step(L.kind))) {
+        // the chain starts once the set-up launches (rotation, tables) are done
+        forked = true;
+        if ((st = hop(s_state, ctx->aux)) != QPE_OK) return st;
+      }
+      if (ahead || after) {
+        if (after && ctrl_waited < L.step - 1) {
+          ctrl_waited = L.step - 1;
+          if ((st = hop(s_state, ctx->aux)) != QPE_OK) return st;
+        }
+        s = ctx->aux;
+        aux_pending = true;
+      } else if (aux_pending) {
+        // every later state-side launch needs the chain's work so far (and
+        // the run ends joined)
+        aux_pending = false;
+        if ((st = hop(ctx->aux, s_state)) != QPE_OK) return st;
+      }
+    }
     TimerScope ts(ctx, timer_of(L.kind));
     switch (L.kind) {
       case BK_SQ:
@@ -557,7 +640,19 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
         QPE_HIP(ctx, launch_batch_elementwise(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
     }
   }
+  if (pipe && aux_pending) {
+    aux_pending = false;
+    return hop(ctx->aux, s_state);
+  }
   return QPE_OK;
+  }();
+  if (result != QPE_OK && aux_pending) {
+    // a failed run still leaves the context stream ordered after the work
+    // already enqueued on the second one (best effort, unchecked)
+    hipEvent_t e = ctx->sched_ev[size_t(next_ev) % ctx->sched_ev.size()];
+    if (hipEventRecord(e, ctx->aux) == hipSuccess) (void)hipStreamWaitEvent(s_state, e, 0);
+  }
+  return result;
 }
 
 const char* const kStatusText[] = {
@@ -655,6 +750,7 @@ static int variant_count(int kernel_class) {
     case QPE_KERNEL_CTRL_F64: return ctrl_f64_variants();
     case QPE_KERNEL_BATCH_CTRL: return 2;
     case QPE_KERNEL_BATCH_GEMM: return 2;
+    case QPE_KERNEL_BATCH_SCHED: return 2;
   }
   return -1;
 }
@@ -672,7 +768,8 @@ QPE_API qpe_status qpe_ctx_set_variant(qpe_ctx* ctx, int kernel_class, int n_mat
   int c = variant_count(kernel_class);
   if (c < 0 || variant < 0 || variant > c) return QPE_ERR_ARG;
   if (n_mat < -1 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
-  const bool batched = kernel_class == QPE_KERNEL_BATCH_CTRL || kernel_class == QPE_KERNEL_BATCH_GEMM;
+  const bool batched = kernel_class == QPE_KERNEL_BATCH_CTRL || kernel_class == QPE_KERNEL_BATCH_GEMM ||
+                       kernel_class == QPE_KERNEL_BATCH_SCHED;
   for (int t = 0; t <= QPE_MAX_N_MAT; ++t)
     if (batched || n_mat < 0 || t == n_mat) ctx->variant[kernel_class][t] = variant;
   return QPE_OK;
@@ -764,6 +861,7 @@ QPE_API qpe_status qpe_autotune_batch(qpe_ctx* ctx, const qpe_problem* problems,
   bool uses[QPE_KERNEL_COUNT] = {};
   for (int i = 0; i < count; ++i) {
     uses[QPE_KERNEL_BATCH_GEMM] |= problems[i].n_meas >= 2;
+    uses[QPE_KERNEL_BATCH_SCHED] |= problems[i].n_meas >= 2 && !(flags & QPE_NO_POLAR);
     uses[QPE_KERNEL_BATCH_CTRL] |= mixed && problems[i].n_mat >= 7;
   }
   if (class_ms)
@@ -831,7 +929,12 @@ static void free_timers(qpe_ctx* ctx) {
 }
 
 QPE_API qpe_status qpe_ctx_destroy(qpe_ctx* ctx) {
-  if (ctx) free_timers(ctx);
+  if (ctx) {
+    free_timers(ctx);
+    DeviceGuard guard(ctx->device);
+    for (hipEvent_t e : ctx->sched_ev) (void)hipEventDestroy(e);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  }
   delete ctx;
   return QPE_OK;
 }
@@ -917,8 +1020,11 @@ QPE_API qpe_status qpe_check_run(const qpe_problem* problems, int count, int for
   return check_workspace(workspace, workspace_bytes, workspace_need(problems, count, form, flags));
 }
 
-QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
-                           void* workspace, size_t workspace_bytes, qpe_report* report) {
+namespace {
+// qpe_run; allow_aux = false keeps a batch on the context stream alone (the
+// two-stream schedule creates its stream and events on first use).
+qpe_status run_checked(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
+                       void* workspace, size_t workspace_bytes, qpe_report* report, bool allow_aux) {
   if (!ctx) return QPE_ERR_ARG;
   qpe_status s = qpe_check_run(problems, count, form, flags, workspace, workspace_bytes, report);
   if (s != QPE_OK) return s;
@@ -926,7 +1032,13 @@ QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count,
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
   if (count == 1) return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report);
-  return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report);
+  return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report, allow_aux);
+}
+}  // namespace
+
+QPE_API qpe_status qpe_run(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
+                           void* workspace, size_t workspace_bytes, qpe_report* report) {
+  return run_checked(ctx, problems, count, form, flags, workspace, workspace_bytes, report, true);
 }
 
 QPE_API qpe_status qpe_run_static(qpe_ctx* ctx, const qpe_problem* problems, int count, int form, unsigned flags,
@@ -943,8 +1055,9 @@ QPE_API qpe_status qpe_run_static(qpe_ctx* ctx, const qpe_problem* problems, int
   hipError_t e = hipSuccess;
   void* ws = static_workspace(ctx->device, &e);
   if (!ws) return hip_fail(ctx, e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
-  // qpe_run ignores the workspace's contents on entry and allocates nothing
-  return qpe_run(ctx, problems, count, form, flags, ws, size_t(QPE_STATIC_WORKSPACE_BYTES), report);
+  // a run ignores the workspace's contents on entry; with one stream it
+  // creates and allocates nothing
+  return run_checked(ctx, problems, count, form, flags, ws, size_t(QPE_STATIC_WORKSPACE_BYTES), report, false);
 }
 
 QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int form, unsigned flags,

@@ -50,7 +50,7 @@ EXPORTS = (
 # Size of the static device workspace of qpe_run_static (QPE_STATIC_WORKSPACE_BYTES).
 STATIC_WORKSPACE_BYTES = 64 << 20
 
-KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2, "batch_ctrl": 3, "batch_gemm": 4}
+KERNEL_CLASSES = {"ctrl_mixed": 0, "zgemm": 1, "ctrl_f64": 2, "batch_ctrl": 3, "batch_gemm": 4, "batch_sched": 5}
 TUNE_MAX_VARIANTS = 12
 
 TIMERS = {"ctrl_gemm": 0, "powers": 1, "split": 2, "qft": 3, "prob": 4, "hlayer": 5}

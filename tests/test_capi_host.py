@@ -142,19 +142,20 @@ def test_estimate_host_checks(L):
 
 
 def test_autotune_and_variant_host_checks(L):
-    chosen = (ctypes.c_int * 5)()
+    chosen = (ctypes.c_int * 6)()
     p = _problems([(8, 5)])
     assert L.qpe_autotune(None, p, 1, 0, 0x100000, 1 << 30, 2, chosen, None) == 1
     v = ctypes.c_int()
     assert L.qpe_ctx_get_variant(None, 0, 5, ctypes.byref(v)) == 1
     pb = _problems([(8, 5), (9, 7)])
     assert L.qpe_autotune_batch(None, pb, 2, 1, 0, 0x100000, 1 << 30, 2, chosen, None) == 1
-    # the batched classes: two variants each
-    for cls in (3, 4):
+    # the batched classes (controlled step, power-chain tiles, schedule): two
+    # variants each
+    for cls in (3, 4, 5):
         c = ctypes.c_int()
         assert L.qpe_kernel_variants(cls, ctypes.byref(c)) == 0 and c.value == 2
     c = ctypes.c_int()
-    assert L.qpe_kernel_variants(5, ctypes.byref(c)) == 1
+    assert L.qpe_kernel_variants(6, ctypes.byref(c)) == 1
 
 
 def test_stage_workspace_sizes(L):

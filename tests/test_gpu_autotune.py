@@ -63,16 +63,18 @@ def test_batch_variants_bitwise(qpe, form):
     try:
         for vc in (0, 1, 2):
             for vg in (0, 1, 2):
-                ctx.set_variant("batch_ctrl", vc)
-                ctx.set_variant("batch_gemm", vg)
-                out = [P.cpu().numpy().copy() for P in run()]
-                if ref is None:
-                    ref = out
-                for i, (a, b) in enumerate(zip(out, ref)):
-                    assert np.array_equal(a, b), (form, vc, vg, i)
+                for vs in (1, 2):
+                    ctx.set_variant("batch_ctrl", vc)
+                    ctx.set_variant("batch_gemm", vg)
+                    ctx.set_variant("batch_sched", vs)
+                    out = [P.cpu().numpy().copy() for P in run()]
+                    if ref is None:
+                        ref = out
+                    for i, (a, b) in enumerate(zip(out, ref)):
+                        assert np.array_equal(a, b), (form, vc, vg, vs, i)
     finally:
-        ctx.set_variant("batch_ctrl", 0)
-        ctx.set_variant("batch_gemm", 0)
+        for name in ("batch_ctrl", "batch_gemm", "batch_sched"):
+            ctx.set_variant(name, 0)
     # and the batch equals the single runs, bit for bit
     for (U, psi, n), P in zip(items, ref):
         assert np.array_equal(qpe.run(U, psi, n, form=form).cpu().numpy(), P)
@@ -85,7 +87,7 @@ def test_autotune_batch(qpe):
     ctx = run.ctx
     try:
         res = run.autotune(reps=1)
-        assert set(res["chosen"]) == {"batch_ctrl", "batch_gemm"}
+        assert set(res["chosen"]) == {"batch_ctrl", "batch_gemm", "batch_sched"}
         for name, v in res["chosen"].items():
             assert 0 <= v <= 2
             assert ctx.get_variant(name, 0) == v and ctx.get_variant(name, 9) == v
@@ -94,5 +96,5 @@ def test_autotune_batch(qpe):
         for a, b in zip(after, before):
             assert np.array_equal(a, b)
     finally:
-        ctx.set_variant("batch_ctrl", 0)
-        ctx.set_variant("batch_gemm", 0)
+        for name in ("batch_ctrl", "batch_gemm", "batch_sched"):
+            ctx.set_variant(name, 0)

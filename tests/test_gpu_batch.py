@@ -97,6 +97,35 @@ def test_graph_replay_matches_eager(qpe, form, flags):
             assert np.array_equal(host(P), e), rep
 
 
+@pytest.mark.parametrize("form,flags", [("mixed", 0), ("fp64", 0), ("mixed", 2)])
+def test_two_stream_schedule(qpe, form, flags):
+    """The batch schedule with the power chain on a second stream: bitwise
+    the one-stream result, eagerly and in every replay of its captured graph
+    (the capture forks the second stream and joins it back)."""
+    probs = config_problems("c4", count=24)
+    say("two-stream schedule, 24-instance batch", form, flags)
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    runner = qpe.Runner(items, form=form, flags=flags)
+    ctx = runner.ctx
+    try:
+        ctx.set_variant("batch_sched", 1)
+        one = [host(P).copy() for P in runner()]
+        ctx.set_variant("batch_sched", 2)
+        two = [host(P).copy() for P in runner()]
+        for a, b in zip(one, two):
+            assert np.array_equal(a, b)
+        graph = qpe.CapturedRun(runner)
+        for rep in range(3):
+            for P in runner.probs:
+                P.fill_(-1.0)
+            host(qpe.run(items[0][0], items[0][1], items[0][2], form))
+            out = graph()
+            for e, P in zip(one, out):
+                assert np.array_equal(host(P), e), rep
+    finally:
+        ctx.set_variant("batch_sched", 0)
+
+
 @pytest.mark.parametrize("flags", [0, 2, 4])
 def test_graph_replay_single_instance(qpe, flags):
     # one instance (the single-run path: gate route, prefix doubling, and the
