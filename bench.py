@@ -49,17 +49,18 @@ EXECUTED = {"split_fp16x3": 3, "split_bf16x6": 6}
 # SHA-256 of the kernel source the counters were taken on. A changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    "31f2f3427a034756": {"fetch_bytes": 262246.4 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
+    "7a01d002301a61b7": {"fetch_bytes": 262307.0 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
                          "profile": "profiles/ctrl_f16x3_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
 # variants of the split-FP16 controlled product that run the kernel whose
-# counters TRAFFIC holds at n = 16, t = 10 (the wide ping-pong kernel: the
-# built-in choice there, variant 8, and the BF16-only designs 3-6, which
-# fall back to it)
-TRAFFIC_VARIANTS = (0, 3, 4, 5, 6, 8)
-CTRL_KERNELS = {1: "k_ctrl_f16x3<128,128>", 2: "k_ctrl_f16x3_db<128,128>", 7: "k_ctrl_f16x3_pp2<128,128>"}
-CTRL_DEFAULT = "k_ctrl_f16x3_pp2<128,256>"
+# counters TRAFFIC holds at n = 16, t = 10 (the persistent wide ping-pong
+# kernel: the built-in choice there, variant 9, and the BF16-only designs
+# 3-6, which fall back to it)
+TRAFFIC_VARIANTS = (0, 3, 4, 5, 6, 9)
+CTRL_KERNELS = {1: "k_ctrl_f16x3<128,128>", 2: "k_ctrl_f16x3_db<128,128>", 7: "k_ctrl_f16x3_pp2<128,128>",
+                8: "k_ctrl_f16x3_pp2<128,256>"}
+CTRL_DEFAULT = "k_ctrl_f16x3_pp2p<128,256>"
 
 
 def traffic_for_current_kernel():

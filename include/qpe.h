@@ -337,8 +337,10 @@ qpe_status qpe_ctx_read_timing(qpe_ctx *ctx, int timer, int *launches, double *t
  * rounding order. */
 enum {
   QPE_KERNEL_CTRL_MIXED = 0, /* split-FP16 / split-BF16 controlled GEMM
-                                (d >= 32); variant 8 (128 x 256 tiles)
-                                exists for split FP16 only            */
+                                (d >= 32); variants 8 (128 x 256 tiles)
+                                and 9 (the same, one persistent workgroup
+                                per CU; the default for d >= 256) exist
+                                for split FP16 only                   */
   QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain          */
   QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
   /* Batched runs (count > 1). One setting per context: n_mat is checked

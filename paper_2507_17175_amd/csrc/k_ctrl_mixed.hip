@@ -788,6 +788,243 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane, S::out_scale(sigma));
 }
 
+// Persistent form of the ping-pong schedule: gridDim.x workgroups (one per
+// CU), workgroup w takes tiles w, w + G, w + 2G, ... (G = gridDim.x, a
+// multiple of 8, so a workgroup stays on one XCD and the XCD remap of the
+// tile order is that of the one-tile-per-workgroup launch) as one stream of
+// K slabs: slab g of the stream is slab g mod nk of tile g / nk. The loads of
+// a tile's first two slabs are issued during the previous tile's last two,
+// and a group stores a finished tile at the start of its next memory phase,
+// while the other group runs its matrix phase; a launch of T tiles thus pays
+// the prologue and the first phase's wait once per workgroup instead of once
+// per tile. Every wave runs the same number of slabs and barriers (the tile
+// count is uniform over the workgroup).
+template <class S, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                uint64_t pmask, float sigma) {
+  constexpr int NG = 256;
+  constexpr int NP = 2 * S::P;
+  static_assert(WM == 2 && WN == 4, "a group is one row half of the tile");
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int FM = TM / 32, FN = TN / 32;
+  constexpr int KS = 16;
+  constexpr int ROW = 24;
+  constexpr int A_PLANE = BM * ROW, B_PLANE = BN * ROW;
+  constexpr int BUF = NP * (A_PLANE + B_PLANE);
+  constexpr int CA = TM * KS / 4 / NG;
+  constexpr int NB = 2 * NP * BN / 2;
+  constexpr int CB = (NB + NG - 1) / NG;
+  static_assert(CA >= 1 && CA * NG * 4 == TM * KS, "tile/thread mismatch");
+  static_assert(NB % NG == 0, "operator chunks per group");
+
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];
+
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  const int M = 1 << (n - 1);
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
+  const int total = tiles_m * tiles_n;
+  const int G = int(gridDim.x), w = int(blockIdx.x);
+  const int count = (total - w + G - 1) / G;  // tiles of this workgroup (>= 1)
+  const int nk = d / KS;                      // a power of two
+  const int lg_nk = 31 - __builtin_clz(unsigned(nk));
+  const int gmax = count * nk - 1;
+  // tile (row block, column tile) of this workgroup's i-th tile
+  auto tile_of = [&](int i) {
+    int L = w + i * G;
+    if ((total & 7) == 0) L = (L & 7) * (total >> 3) + (L >> 3);
+    return make_int2(L / tiles_n, L % tiles_n);
+  };
+
+  // wave-uniform values live in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2, tg = tid & (NG - 1);
+  const int wi0 = (wave / WN) * TM, wj0 = (wave % WN) * TN;
+
+  // loads follow the tile of the slab they fetch
+  int load_tile = -1, lj0 = 0;
+  const float2* src_row[CA];
+  auto set_load_tile = [&](int i) {
+    const int2 tl = tile_of(i);
+    load_tile = i;
+    lj0 = tl.y * BN;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tg + q * NG;
+      int gi = min(tl.x * BM + wi0 + c / 4, M - 1);
+      int64_t j = step_row(gi, k, pmask);
+      src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+    }
+  };
+
+  float4 ra[CA][2];
+  u32x4 rb[CB];
+  auto load_a = [&](int g) {
+    const int k0 = (g & (nk - 1)) * KS;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4* p = reinterpret_cast<const float4*>(src_row[q] + k0);
+      ra[q][0] = p[0];
+      ra[q][1] = p[1];
+    }
+  };
+  // operator chunk q of a thread: plane (grp NB + q NG) / 2BN (wave-uniform,
+  // as NG divides 2BN), column and half from the thread's index; the address
+  // is a wave-uniform base plus a 32-bit per-lane offset
+  static_assert((BN * 2) % NG == 0 && NB % (BN * 2) == 0, "operator chunk layout");
+  auto load_b = [&](int g) {
+    const int sl = g & (nk - 1);
+    // (the empty asm keeps the compiler from hoisting one 64-bit address per
+    // chunk out of the loop, which costs eight registers)
+    uint32_t lo = uint32_t((tg >> 1) * kPlaneBlock + 8 * (tg & 1));
+    asm volatile("" : "+v"(lo));
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int pl = (grp * NB + q * NG) / (BN * 2);
+      const uint32_t off = lo + uint32_t((q * NG) % (BN * 2) / 2 * kPlaneBlock);
+      const uint16_t* base = planes + (int64_t(pl) * dd + (int64_t(sl) * d + lj0) * kPlaneBlock);
+      rb[q] = *reinterpret_cast<const u32x4*>(base + off);
+    }
+  };
+  typename S::v4 pc[CA][NP];
+  auto split_part = [&](int u) {
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      const float4 x = ra[q][u >> 1];
+      typename S::elem o[S::P];
+      S::split((u & 1) ? x.z : x.x, sigma, o);
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2][u] = o[pc2];
+      S::split((u & 1) ? x.w : x.y, sigma, o);
+#pragma unroll
+      for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2 + 1][u] = o[pc2];
+    }
+  };
+  auto write_a = [&](int b) {
+    uint16_t* base = lds + b * BUF;
+#pragma unroll
+    for (int q = 0; q < CA; ++q) {
+      int c = tg + q * NG;
+      int r = wi0 + c / 4, kq = c & 3;
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl)
+        *reinterpret_cast<typename S::v4*>(base + pl * A_PLANE + r * ROW + 4 * kq) = pc[q][pl];
+    }
+  };
+  auto write_b = [&](int b) {
+    uint16_t* base = lds + b * BUF + NP * A_PLANE;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int pl = (grp * NB + q * NG) / (BN * 2);
+      const int wv = (q * NG + tg) % (BN * 2);
+      *reinterpret_cast<u32x4*>(base + pl * B_PLANE + (wv >> 1) * ROW + 8 * (wv & 1)) = rb[q];
+    }
+  };
+
+  f32x16 acc_re[FM][FN], acc_im[FM][FN];
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          acc_re[x][y][v] = 0.f;
+          acc_im[x][y][v] = 0.f;
+        }
+  };
+  const float oscale = S::out_scale(sigma);
+  auto store_acc = [&](int i) {
+    const int2 tl = tile_of(i);
+    store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, tl.x * BM + wi0, tl.y * BN + wj0, lane, oscale);
+  };
+  zero_acc();
+
+  const int lr = lane & 31, ko = (lane >> 5) * 8;
+  set_load_tile(0);
+  load_a(0);
+  load_b(0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_part(u);
+  write_a(0);
+  write_b(0);
+  load_b(1);  // nk >= 2: slab 1 is in tile 0; loaded in the loop's order
+  load_a(1);
+  __syncthreads();
+  if (grp == 1) __syncthreads();
+
+  for (int g = 0; g <= gmax; ++g) {
+    const int nb = (g + 1) & 1, g2 = min(g + 2, gmax);
+    // memory phase: the operator chunks of slab g+1, the finished tile (a
+    // group's first memory phase of a new tile), the fragments of slab g and
+    // the loads of slab g+2, in the tile of g+2
+    write_b(nb);
+    if ((g & (nk - 1)) == 0 && g > 0) {
+      __builtin_amdgcn_sched_barrier(0);
+      store_acc((g >> lg_nk) - 1);
+      zero_acc();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const uint16_t* base = lds + (g & 1) * BUF;
+    typedef typename S::v8 V8;
+    V8 av[FM][NP], bv[FN][NP], bneg[FN][S::P];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl)
+        av[x][pl] = *reinterpret_cast<const V8*>(base + pl * A_PLANE + (wi0 + 32 * x + lr) * ROW + ko);
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl)
+        bv[y][pl] = *reinterpret_cast<const V8*>(base + NP * A_PLANE + pl * B_PLANE + (wj0 + 32 * y + lr) * ROW + ko);
+    if ((g2 >> lg_nk) != load_tile) set_load_tile(g2 >> lg_nk);
+    load_b(g2);
+    constexpr bool kNeg = FN > 1;
+    if constexpr (!kNeg) {
+#pragma unroll
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int pc2 = 0; pc2 < S::P; ++pc2) bneg[y][pc2] = negate(bv[y][2 * pc2 + 1]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    // matrix phase, with the split and store of the group's rows of slab g+1
+    mma_pieces<S, FM, FN, 0, kNeg>(acc_re, acc_im, av, bv, bneg);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_part(u);
+    write_a(nb);
+    load_a(g2);
+    constexpr int kMfma = FM * FN * 4 * S::NPAIR;
+    constexpr int kRest = kMfma - S::kValuGroups - S::kDsGroups - 2;
+    static_assert(kRest >= 0, "issue plan longer than the slab's MFMAs");
+#pragma unroll
+    for (int i = 0; i < S::kValuGroups; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, S::kValuPer, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < S::kDsGroups; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, kRest, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (grp == 0) __syncthreads();
+
+  store_acc(count - 1);
+}
+
 template <int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(512) k_ctrl_bf16x6_pp2(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                           const uint16_t* __restrict__ planes, int n, int t, int k,
@@ -804,6 +1041,14 @@ __global__ void __launch_bounds__(512) k_ctrl_f16x3_pp2(float2* __restrict__ buf
   const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
   const int2 tile = xcd_tile(tiles_m, tiles_n);
   ctrl_pp2_tile<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, tile.x, tile.y, *sigma);
+}
+
+// The persistent wide-tile kernel (gridDim.x workgroups, a multiple of 8).
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(512) k_ctrl_f16x3_pp2p(float2* __restrict__ buf0, float2* __restrict__ buf1,
+                                                          const uint16_t* __restrict__ planes, int n, int t, int k,
+                                                          uint64_t pmask, const float* __restrict__ sigma) {
+  ctrl_pp2p_tiles<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, *sigma);
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -1395,22 +1640,45 @@ hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const ui
 // Split-FP16 controlled step: the tile choices of the default split-BF16
 // path (variant 1: the 4-wave kernel throughout, 2: the in-step schedule
 // for every size, 7: ping-pong for d >= 128; the BF16-only designs 3-6 fall
-// back to the default), and variant 8, the default from d = 256 on: the
-// ping-pong schedule on 128 x 256 tiles (64 x 64 outputs per wave), whose
-// matrix phase holds 48 MFMAs per wave like the split-BF16 kernel's (the
-// 128 x 128 tile gives each phase only 24, and the fixed cost of a phase
-// then weighs twice as much), and which reads the operator planes half as
-// often per row.
+// back to the default), variant 8: the ping-pong schedule on 128 x 256 tiles
+// (64 x 64 outputs per wave), whose matrix phase holds 48 MFMAs per wave
+// like the split-BF16 kernel's (the 128 x 128 tile gives each phase only 24,
+// and the fixed cost of a phase then weighs twice as much), and which reads
+// the operator planes half as often per row; variant 9, the default from
+// d = 256 on (launches of 512 tiles or more): variant 8 in its persistent
+// form (2 % faster at c3, 0.3 % at c2).
+// Compute units of the current device (the persistent kernel's grid).
+int cu_count() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] <= 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cached[dev] = c;
+  }
+  return cached[dev];
+}
+
 hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                            hipStream_t s, int variant, const float* sigma) {
   // Variants 7 and 8 choose the schedule of launches with enough tiles to
   // fill the chip (>= 256); smaller ones (early prefix-doubling steps) keep
   // the default choices.
   const int64_t wide_tiles = ((int64_t(1) << (n - 1)) + 127) / 128 * (t >= 8 ? (1 << t) / 256 : 0);
-  if (t >= 8 && ((variant == 8 && wide_tiles >= 256) ||
-                 ((variant == 0 || (variant >= 3 && variant <= 6)) && wide_tiles >= 512)))
+  const bool dflt = variant == 0 || (variant >= 3 && variant <= 6);
+  if (t >= 8 && ((variant == 9 && wide_tiles >= 256) || (dflt && wide_tiles >= 512))) {
+    // persistent: one workgroup per CU (a multiple of 8, for the XCD order)
+    int g = cu_count() & ~7;
+    if (g < 8) g = 8;
+    if (int64_t(g) > wide_tiles) g = int(wide_tiles);
+    hipLaunchKernelGGL((k_ctrl_f16x3_pp2p<128, 256, 2, 4>), dim3(g), dim3(512), 0, s, buf0, buf1, planes, n, t, k,
+                       pmask, sigma);
+    return hipGetLastError();
+  }
+  if (t >= 8 && variant == 8 && wide_tiles >= 256)
     return launch<512>(k_ctrl_f16x3_pp2<128, 256, 2, 4>, 128, 256, buf0, buf1, planes, n, t, k, pmask, s, sigma);
-  if (variant == 8) variant = 0;
+  if (variant >= 8) variant = 0;
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_f16x3<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s, sigma);
     if (t == 6) return launch<256>(k_ctrl_f16x3<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s, sigma);
@@ -1431,12 +1699,12 @@ hipError_t launch_ctrl_f16(float2* buf0, float2* buf1, const uint16_t* planes, i
 
 }  // namespace
 
-int ctrl_mixed_variants() { return 8; }
+int ctrl_mixed_variants() { return 9; }
 
 hipError_t launch_ctrl_mixed(float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k, uint64_t pmask,
                              hipStream_t s, int variant, const float* sigma_f16) {
   if (sigma_f16) return launch_ctrl_f16(buf0, buf1, planes, n, t, k, pmask, s, variant, sigma_f16);
-  if (variant == 8) variant = 0;  // the wide tile is a split-FP16 kernel
+  if (variant >= 8) variant = 0;  // the wide tiles are split-FP16 kernels
   if (variant == 1) {
     if (t >= 7) return launch<256>(k_ctrl_bf16x6<128, 128, 2, 2>, 128, 128, buf0, buf1, planes, n, t, k, pmask, s);
     if (t == 6) return launch<256>(k_ctrl_bf16x6<128, 64, 2, 2>, 128, 64, buf0, buf1, planes, n, t, k, pmask, s);

@@ -71,3 +71,27 @@ def test_zgemm_variants(qpe, form):
     for v, P in out.items():
         assert float(np.abs(P - out[0]).max()) <= (1e-12 if form == "fp64" else 1e-7), v
         assert float(np.abs(P - ref).max()) <= (1e-11 if form == "fp64" else 1e-6), v
+
+
+@pytest.mark.parametrize("flags", [0, 2], ids=["gate_route", "prefix_doubling"])
+@pytest.mark.parametrize("n,t", [(14, 10), (15, 10), (16, 9), (17, 8)])
+def test_wide_tile_variants_bitwise(qpe, n, t, flags):
+    """The 128 x 256 tile schedules (variant 8, and variant 9, its persistent
+    form and the default from 512 tiles: one workgroup per CU taking 1, 2 or
+    more tiles in turn) at sizes with at least 256 such tiles: bit for bit
+    the default run, and within 1e-6 of the Fejer closed form of the
+    eigenvector input."""
+    p = make_problem(n, t, np.random.default_rng(500 + n + t))
+    U, psi = torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda()
+    ctx = qpe.context(0)
+    out = {}
+    try:
+        for v in (0, 8, 9):
+            ctx.set_variant("ctrl_mixed", v)
+            out[v] = qpe.run(U, psi, n, form="mixed", flags=flags).cpu().numpy()
+    finally:
+        ctx.set_variant("ctrl_mixed", 0)
+    for v in (8, 9):
+        assert np.array_equal(out[v], out[0]), v
+    F = O.fejer(float(p.phis[0]), n)
+    assert float(np.abs(out[0] - F).max()) <= 1e-6
