@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_F16_TFLOPS = 2500.0  # dense FP16 and BF16 matrix cores
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3  # FP32 vector ALUs
 PEAK_HBM_GBS = 8000.0
 
 # "dtype" is the matrix-core type of the dominant kernel; the whole path:
@@ -464,14 +465,23 @@ def main():
     achieved = flops_per_launch / avg_s / 1e12
     ctx = qpe.context(torch.cuda.current_device())
     ctrl_variant = ctx.get_variant("ctrl_mixed", t) if t >= 5 else None
-    roofline = {
-        "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, CTRL_DEFAULT)} (controlled product, split-FP16 x3 on MFMA; "
-                   f"variant {ctrl_variant})") if t >= 5 else "k_ctrl_small",
-        "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_F16_TFLOPS, 4),
-        "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),
-        "flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt,
-    }
+    if t >= 5:
+        roofline = {
+            "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, CTRL_DEFAULT)} (controlled product, split-FP16 x3 on MFMA; "
+                       f"variant {ctrl_variant})"),
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_F16_TFLOPS, 4),
+            "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),
+        }
+    else:
+        # d <= 16: one thread per row on the vector ALUs in FP32 (no split);
+        # a launch this small is decided by its latency, not by the ALUs
+        roofline = {
+            "kernel": "k_ctrl_small (controlled product on the vector ALUs, FP32)",
+            "bound": "alu", "achieved": round(achieved, 6), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 8), "executed_frac": round(achieved / PEAK_FP32_TFLOPS, 8),
+        }
+    roofline.update({"flops_per_launch": flops_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g_cnt})
     # traffic: HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE), or null
     # valid for the kernel the counters were taken on: the built-in choice at
     # this size (variant 0) or the same kernel picked explicitly
