@@ -356,9 +356,11 @@ enum {
                                  that the squares and Gram products of step
                                  k+1 overlap the controlled products of step
                                  k; joined back into the context stream before
-                                 the run returns, also when it fails. With
-                                 per-kernel timing on, or in qpe_run_static
-                                 (which creates nothing), one stream. */
+                                 the run returns, also when it fails. While
+                                 per-kernel timers record (timing enabled and
+                                 a non-empty timing mask), or in
+                                 qpe_run_static (which creates nothing), one
+                                 stream. */
   QPE_KERNEL_COUNT = 6
 };
 qpe_status qpe_kernel_variants(int kernel_class, int *count);

@@ -826,7 +826,8 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
   const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
   const int total = tiles_m * tiles_n;
   const int G = int(gridDim.x), w = int(blockIdx.x);
-  const int count = (total - w + G - 1) / G;  // tiles of this workgroup (>= 1)
+  const int count = (total - w + G - 1) / G;  // tiles of this workgroup
+  if (count <= 0) return;                     // (the launcher keeps G <= total)
   const int nk = d / KS;                      // a power of two
   const int lg_nk = 31 - __builtin_clz(unsigned(nk));
   const int gmax = count * nk - 1;

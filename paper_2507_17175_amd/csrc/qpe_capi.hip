@@ -555,8 +555,10 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
   // state-side launch waits for the chain through step k; the second part
   // of power step k waits for the state side through step k-1 (the plan
   // lists, for each k, the chain's launches before the state's). Per-kernel
-  // timers bracket launches on the context stream, so timing keeps one.
-  const bool pipe = allow_aux && polar && ctx->variant[QPE_KERNEL_BATCH_SCHED][0] != 1 && !ctx->timing;
+  // timers bracket launches on the context stream, so while any timer class
+  // records, the run keeps one stream.
+  const bool timers = ctx->timing && ctx->timer_mask != 0u;
+  const bool pipe = allow_aux && polar && ctx->variant[QPE_KERNEL_BATCH_SCHED][0] != 1 && !timers;
   int next_ev = 0;
   bool forked = false, aux_pending = false;
   int ctrl_waited = -1;  // the last step whose state-side launches the chain waited for
