@@ -352,7 +352,8 @@ enum {
   QPE_KERNEL_BATCH_SCHED = 5, /* schedule of a batched run with the polar
                                  step: 1 one stream, 2 (default) the power
                                  chain on a second stream of the context
-                                 (created, with its events, on first use), so
+                                 (created with its events by qpe_ctx_create;
+                                 if that failed, by the first batched run), so
                                  that the squares and Gram products of step
                                  k+1 overlap the controlled products of step
                                  k; joined back into the context stream before

@@ -737,9 +737,20 @@ QPE_API qpe_status qpe_ctx_create(qpe_ctx** out, int device, void* stream) {
   if (const char* f = std::getenv("QPE_FAULT_INJECT")) c->fault_at = std::strtol(f, nullptr, 10);
   {
     // set-up of the static workspace on this device (its failure only
-    // affects qpe_run_static, which then reports it)
+    // affects qpe_run_static, which then reports it), and the second stream
+    // and events of the two-stream batch schedule, created here so that a
+    // first batched run under graph capture creates nothing (best effort:
+    // the first batched run retries what failed, and reports a failure)
     DeviceGuard guard(device);
-    if (guard.ok) fetch_static_workspace(device);
+    if (guard.ok) {
+      fetch_static_workspace(device);
+      if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) c->aux = nullptr;
+      for (int i = 0; i < kSchedEvents; ++i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) break;
+        c->sched_ev.push_back(e);
+      }
+    }
   }
   *out = c;
   return QPE_OK;

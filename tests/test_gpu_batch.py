@@ -126,6 +126,28 @@ def test_two_stream_schedule(qpe, form, flags):
         ctx.set_variant("batch_sched", 0)
 
 
+def test_capture_first_run_of_a_fresh_context(qpe):
+    """A batched run captured into a HIP graph as the very first call on a new
+    context: the context already holds the second stream and its events, so
+    the capture creates nothing; every replay equals an eager run."""
+    probs = config_problems("c4", count=24)
+    say("capture as the first call of a fresh context")
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    runner = qpe.Runner(items, form="mixed")
+    eager = [host(P).copy() for P in runner()]
+    runner.ctx = qpe.Context(0)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        runner()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for P in runner.probs:
+            P.fill_(-1.0)
+        graph.replay()
+        for e, P in zip(eager, runner.probs):
+            assert np.array_equal(host(P), e), rep
+
+
 @pytest.mark.parametrize("flags", [0, 2, 4])
 def test_graph_replay_single_instance(qpe, flags):
     # one instance (the single-run path: gate route, prefix doubling, and the
