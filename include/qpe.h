@@ -345,8 +345,12 @@ enum {
   QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
   /* Batched runs (count > 1). One setting per context: n_mat is checked
    * but the choice applies to every instance size. */
-  QPE_KERNEL_BATCH_CTRL = 3, /* grouped split-BF16 controlled step, d >= 128:
-                                1 in-step schedule, 2 ping-pong (default) */
+  QPE_KERNEL_BATCH_CTRL = 3, /* grouped controlled step, d >= 128: 1 in-step
+                                schedule (d = 128), 2 (default) ping-pong with
+                                one tile per workgroup, 3 ping-pong with the
+                                split-FP16 step of the d >= 256 instances on
+                                one persistent workgroup per CU (when those
+                                instances share one d) */
   QPE_KERNEL_BATCH_GEMM = 4, /* grouped FP64 power-chain products: 1 32x32
                                 tiles (default), 2 64x64 tiles for d >= 64 */
   QPE_KERNEL_BATCH_SCHED = 5, /* schedule of a batched run with the polar

@@ -788,21 +788,33 @@ __device__ __forceinline__ void ctrl_pp2_tile(float2* __restrict__ buf0, float2*
   store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, i0 + wi0, j0 + wj0, lane, S::out_scale(sigma));
 }
 
+// One tile of a persistent launch: the buffers and operator of its instance,
+// the register size and step, and its row block and column tile.
+struct PTile {
+  float2* buf0;
+  float2* buf1;
+  const uint16_t* planes;
+  int n, k;
+  uint64_t pmask;
+  int tm, tn;
+  float sigma;
+};
+
 // Persistent form of the ping-pong schedule: gridDim.x workgroups (one per
-// CU), workgroup w takes tiles w, w + G, w + 2G, ... (G = gridDim.x, a
-// multiple of 8, so a workgroup stays on one XCD and the XCD remap of the
-// tile order is that of the one-tile-per-workgroup launch) as one stream of
-// K slabs: slab g of the stream is slab g mod nk of tile g / nk. The loads of
-// a tile's first two slabs are issued during the previous tile's last two,
-// and a group stores a finished tile at the start of its next memory phase,
-// while the other group runs its matrix phase; a launch of T tiles thus pays
-// the prologue and the first phase's wait once per workgroup instead of once
-// per tile. Every wave runs the same number of slabs and barriers (the tile
-// count is uniform over the workgroup).
-template <class S, int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float2* __restrict__ buf1,
-                                                const uint16_t* __restrict__ planes, int n, int t, int k,
-                                                uint64_t pmask, float sigma) {
+// CU), workgroup w takes tiles w, w + G, w + 2G, ... of the launch's `total`
+// (G = gridDim.x, a multiple of 8, so a workgroup stays on one XCD and the
+// XCD remap of the tile order is that of the one-tile-per-workgroup launch)
+// as one stream of K slabs: slab g of the stream is slab g mod nk of tile
+// g / nk. prov(L) describes tile L of the launch; all tiles have d = 2^t
+// (the tiles of a batched launch may belong to different instances). The
+// loads of a tile's first two slabs are issued during the previous tile's
+// last two, and a group stores a finished tile at the start of its next
+// memory phase, while the other group runs its matrix phase; a launch of T
+// tiles thus pays the prologue and the first phase's wait once per
+// workgroup instead of once per tile. Every wave runs the same number of
+// slabs and barriers (the tile count is uniform over the workgroup).
+template <class S, int BM, int BN, int WM, int WN, class Prov>
+__device__ __forceinline__ void ctrl_pp2p_tiles(int t, int total, Prov prov) {
   constexpr int NG = 256;
   constexpr int NP = 2 * S::P;
   static_assert(WM == 2 && WN == 4, "a group is one row half of the tile");
@@ -822,20 +834,17 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
 
   const int d = 1 << t;
   const int64_t dd = int64_t(d) * d;
-  const int M = 1 << (n - 1);
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = d / BN;
-  const int total = tiles_m * tiles_n;
   const int G = int(gridDim.x), w = int(blockIdx.x);
   const int count = (total - w + G - 1) / G;  // tiles of this workgroup
   if (count <= 0) return;                     // (the launcher keeps G <= total)
   const int nk = d / KS;                      // a power of two
   const int lg_nk = 31 - __builtin_clz(unsigned(nk));
   const int gmax = count * nk - 1;
-  // tile (row block, column tile) of this workgroup's i-th tile
+  // this workgroup's i-th tile
   auto tile_of = [&](int i) {
     int L = w + i * G;
     if ((total & 7) == 0) L = (L & 7) * (total >> 3) + (L >> 3);
-    return make_int2(L / tiles_n, L % tiles_n);
+    return prov(L);
   };
 
   // wave-uniform values live in scalar registers
@@ -845,21 +854,27 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
 
   // loads follow the tile of the slab they fetch
   int load_tile = -1, lj0 = 0;
+  const uint16_t* lplanes = nullptr;
+  float lsigma = 1.0f;
   const float2* src_row[CA];
   auto set_load_tile = [&](int i) {
-    const int2 tl = tile_of(i);
+    const PTile pt = tile_of(i);
+    const int M = 1 << (pt.n - 1);
     load_tile = i;
-    lj0 = tl.y * BN;
+    lj0 = pt.tn * BN;
+    lplanes = pt.planes;
+    lsigma = pt.sigma;
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
       int c = tg + q * NG;
-      int gi = min(tl.x * BM + wi0 + c / 4, M - 1);
-      int64_t j = step_row(gi, k, pmask);
-      src_row[q] = (src_buffer(j, pmask) ? buf1 : buf0) + j * d + 4 * (c & 3);
+      int gi = min(pt.tm * BM + wi0 + c / 4, M - 1);
+      int64_t j = step_row(gi, pt.k, pt.pmask);
+      src_row[q] = (src_buffer(j, pt.pmask) ? pt.buf1 : pt.buf0) + j * d + 4 * (c & 3);
     }
   };
 
   float4 ra[CA][2];
+  float ra_sigma = 1.0f;  // the state scale of the tile whose rows ra holds
   u32x4 rb[CB];
   auto load_a = [&](int g) {
     const int k0 = (g & (nk - 1)) * KS;
@@ -884,7 +899,7 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
     for (int q = 0; q < CB; ++q) {
       const int pl = (grp * NB + q * NG) / (BN * 2);
       const uint32_t off = lo + uint32_t((q * NG) % (BN * 2) / 2 * kPlaneBlock);
-      const uint16_t* base = planes + (int64_t(pl) * dd + (int64_t(sl) * d + lj0) * kPlaneBlock);
+      const uint16_t* base = lplanes + (int64_t(pl) * dd + (int64_t(sl) * d + lj0) * kPlaneBlock);
       rb[q] = *reinterpret_cast<const u32x4*>(base + off);
     }
   };
@@ -894,10 +909,10 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
     for (int q = 0; q < CA; ++q) {
       const float4 x = ra[q][u >> 1];
       typename S::elem o[S::P];
-      S::split((u & 1) ? x.z : x.x, sigma, o);
+      S::split((u & 1) ? x.z : x.x, ra_sigma, o);
 #pragma unroll
       for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2][u] = o[pc2];
-      S::split((u & 1) ? x.w : x.y, sigma, o);
+      S::split((u & 1) ? x.w : x.y, ra_sigma, o);
 #pragma unroll
       for (int pc2 = 0; pc2 < S::P; ++pc2) pc[q][2 * pc2 + 1][u] = o[pc2];
     }
@@ -935,10 +950,10 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
           acc_im[x][y][v] = 0.f;
         }
   };
-  const float oscale = S::out_scale(sigma);
   auto store_acc = [&](int i) {
-    const int2 tl = tile_of(i);
-    store_tile<FM, FN>(acc_re, acc_im, buf0, buf1, M, d, k, pmask, tl.x * BM + wi0, tl.y * BN + wj0, lane, oscale);
+    const PTile pt = tile_of(i);
+    store_tile<FM, FN>(acc_re, acc_im, pt.buf0, pt.buf1, 1 << (pt.n - 1), d, pt.k, pt.pmask, pt.tm * BM + wi0,
+                       pt.tn * BN + wj0, lane, S::out_scale(pt.sigma));
   };
   zero_acc();
 
@@ -946,6 +961,7 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
   set_load_tile(0);
   load_a(0);
   load_b(0);
+  ra_sigma = lsigma;
 #pragma unroll
   for (int u = 0; u < 4; ++u) split_part(u);
   write_a(0);
@@ -998,6 +1014,7 @@ __device__ __forceinline__ void ctrl_pp2p_tiles(float2* __restrict__ buf0, float
     for (int u = 0; u < 4; ++u) split_part(u);
     write_a(nb);
     load_a(g2);
+    ra_sigma = lsigma;
     constexpr int kMfma = FM * FN * 4 * S::NPAIR;
     constexpr int kRest = kMfma - S::kValuGroups - S::kDsGroups - 2;
     static_assert(kRest >= 0, "issue plan longer than the slab's MFMAs");
@@ -1049,7 +1066,11 @@ template <int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(512) k_ctrl_f16x3_pp2p(float2* __restrict__ buf0, float2* __restrict__ buf1,
                                                           const uint16_t* __restrict__ planes, int n, int t, int k,
                                                           uint64_t pmask, const float* __restrict__ sigma) {
-  ctrl_pp2p_tiles<F16x3, BM, BN, WM, WN>(buf0, buf1, planes, n, t, k, pmask, *sigma);
+  const int tiles_m = ((1 << (n - 1)) + BM - 1) / BM, tiles_n = (1 << t) / BN;
+  const float sg = *sigma;
+  ctrl_pp2p_tiles<F16x3, BM, BN, WM, WN>(t, tiles_m * tiles_n, [=](int L) {
+    return PTile{buf0, buf1, planes, n, k, pmask, L / tiles_n, L % tiles_n, sg};
+  });
 }
 
 // ----------------------------------------------------------------- variant 4
@@ -1629,6 +1650,35 @@ kb_ctrl_mixed(int step, const InstDesc* __restrict__ desc, const int32_t* __rest
     ctrl_pp2_tile<S, 128, 128, 2, 4>(s0, s1, planes, n, D.t, k, pmask, tm, tn, sigma);
 }
 
+// The split-FP16 controlled step of the batch's instances with d = 2^t >=
+// 256 (all of one t) on one persistent workgroup per CU: the workgroups take
+// the launch's tiles in turn across the instances, each tile's buffers,
+// operator and state scale from its instance's descriptor.
+__global__ void __launch_bounds__(512) kb_ctrl_wide_persistent(int step, const InstDesc* __restrict__ desc,
+                                                                const int32_t* __restrict__ table, int bflags,
+                                                                int total, int t) {
+  const bool dbl = (bflags & kBatchDoubling) != 0, pol = (bflags & kBatchPolar) != 0;
+  ctrl_pp2p_tiles<F16x3, 128, 256, 2, 4>(t, total, [=](int L) {
+    int64_t local;
+    const int i = find_member(table, L, &local);
+    const InstDesc D = load_desc(desc, i);
+    const RunLayout R = run_layout(D.n, D.t, true, pol);
+    float2* s0 = reinterpret_cast<float2*>(D.ws + R.state0);
+    // prefix doubling: rows [0, 2^k) -> rows [2^k, 2^(k+1)) of state0
+    float2* s1 = dbl ? s0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<float2*>(D.ws + R.state1);
+    const int tiles_n = (1 << D.t) / 256;
+    return PTile{s0,
+                 s1,
+                 reinterpret_cast<const uint16_t*>(D.ws + R.planes),
+                 dbl ? step + 1 : D.n,
+                 step,
+                 dbl ? kDoubling : (uint64_t(1) << step) - 1,
+                 int(local / tiles_n),
+                 int(local % tiles_n),
+                 *reinterpret_cast<const float*>(D.ws + R.scratch + 8 * kScratchSigma)};
+  });
+}
+
 template <int NT, typename K, typename... X>
 hipError_t launch(K kernel, int BM, int BN, float2* buf0, float2* buf1, const uint16_t* planes, int n, int t, int k,
                   uint64_t pmask, hipStream_t s, X... extra) {
@@ -1782,8 +1832,15 @@ hipError_t launch_ns_product(float2* x32, float2* xe, const uint16_t* planes, in
 }
 
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                   int bflags, hipStream_t s) {
+                                   int bflags, hipStream_t s, int wide_t) {
   const int p = bflags;
+  if ((bflags & kBatchF16) && kind == BK_CTRL_M256 && (bflags & kBatchPersistent) && wide_t >= 8 &&
+      tiles >= 512 && tiles < (int64_t(1) << 31)) {
+    int g = cu_count() & ~7;
+    if (g < 8) g = 8;
+    hipLaunchKernelGGL(kb_ctrl_wide_persistent, dim3(g), dim3(512), 0, s, step, desc, table, p, int(tiles), wide_t);
+    return hipGetLastError();
+  }
   if (bflags & kBatchF16) {
     switch (kind) {
       case BK_CTRL_M32:

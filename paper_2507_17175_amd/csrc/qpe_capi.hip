@@ -472,7 +472,9 @@ int timer_of(int kind) {
 int batch_variant_flags(const qpe_ctx* ctx) {
   int f = 0;
   if (ctx->variant[QPE_KERNEL_BATCH_GEMM][0] == 2) f |= kBatchGemm64;
-  if (ctx->variant[QPE_KERNEL_BATCH_CTRL][0] == 1) f |= kBatchCtrlInStep;
+  const int vc = ctx->variant[QPE_KERNEL_BATCH_CTRL][0];
+  if (vc == 1) f |= kBatchCtrlInStep;
+  if (vc == 3) f |= kBatchPersistent;
   return f;
 }
 
@@ -546,6 +548,12 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
   }
   bool stage_small = false;  // an instance with d = 8 or 16 takes the small controlled step
   for (int i = 0; i < count; ++i) stage_small |= p[i].n_mat == 3 || p[i].n_mat == 4;
+  // the t shared by every instance with d >= 256, or 0 (the persistent wide
+  // controlled step needs one d per launch)
+  int wide_t = -1;
+  for (int i = 0; i < count; ++i)
+    if (p[i].n_mat >= 8) wide_t = (wide_t < 0 || wide_t == p[i].n_mat) ? p[i].n_mat : 0;
+  if (wide_t < 0) wide_t = 0;
   const int nl = int(P.launches.size());
   for (int first = 0; first < nl; first += kBatchLaunchChunk) {
     int c = nl - first < kBatchLaunchChunk ? nl - first : kBatchLaunchChunk;
@@ -619,7 +627,7 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_NS_M32:
       case BK_NS_M64:
       case BK_NS_M128:
-        QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, bf, s));
+        QPE_HIP(ctx, launch_batch_ctrl_mixed(L.kind, L.step, desc, tab, tiles, bf, s, wide_t));
         break;
       case BK_CTRL_F64:
         QPE_HIP(ctx, launch_batch_ctrl_f64(L.step, desc, tab, tiles, bf, s));
@@ -761,7 +769,7 @@ static int variant_count(int kernel_class) {
     case QPE_KERNEL_CTRL_MIXED: return ctrl_mixed_variants();
     case QPE_KERNEL_ZGEMM: return zgemm_variants();
     case QPE_KERNEL_CTRL_F64: return ctrl_f64_variants();
-    case QPE_KERNEL_BATCH_CTRL: return 2;
+    case QPE_KERNEL_BATCH_CTRL: return 3;
     case QPE_KERNEL_BATCH_GEMM: return 2;
     case QPE_KERNEL_BATCH_SCHED: return 2;
   }

@@ -302,6 +302,10 @@ __host__ __device__ inline int64_t rot_hash_blocks(int t) {
 constexpr int kBatchPolar = 1, kBatchDoubling = 2, kBatchGemm64 = 4, kBatchCtrlInStep = 8;
 // kBatchF16: the controlled steps of d >= 32 run as split-FP16 products
 constexpr int kBatchF16 = 64;
+// kBatchPersistent (batched controlled-step variant 3): the split-FP16
+// controlled step of the d >= 256 instances runs on one persistent workgroup
+// per CU (the launcher applies it when those instances share one d)
+constexpr int kBatchPersistent = 128;
 // target rotation mode (RotMode) in bits 4-5
 constexpr int kBatchRotShift = 4;
 __host__ __device__ inline int batch_rot_mode(int bflags) { return (bflags >> kBatchRotShift) & 3; }
@@ -584,7 +588,7 @@ hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const in
 hipError_t launch_batch_ctrl_f64(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, int bflags,
                                  hipStream_t s);
 hipError_t launch_batch_ctrl_mixed(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,
-                                   int bflags, hipStream_t s);
+                                   int bflags, hipStream_t s, int wide_t = 0);
 // stage: some instance of the launch has d = 8 or 16 (rows staged in LDS).
 hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
                                    bool stage, int bflags, hipStream_t s);

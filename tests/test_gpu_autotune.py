@@ -61,7 +61,7 @@ def test_batch_variants_bitwise(qpe, form):
     ctx = run.ctx
     ref = None
     try:
-        for vc in (0, 1, 2):
+        for vc in (0, 1, 2, 3):
             for vg in (0, 1, 2):
                 for vs in (1, 2):
                     ctx.set_variant("batch_ctrl", vc)
@@ -89,9 +89,10 @@ def test_autotune_batch(qpe):
         res = run.autotune(reps=1)
         assert set(res["chosen"]) == {"batch_ctrl", "batch_gemm", "batch_sched"}
         for name, v in res["chosen"].items():
-            assert 0 <= v <= 2
+            assert 0 <= v <= qpe.kernel_variants(name)
             assert ctx.get_variant(name, 0) == v and ctx.get_variant(name, 9) == v
-            assert len(res["ms_per_batch"][name]) == 3 and all(m > 0 for m in res["ms_per_batch"][name])
+            assert len(res["ms_per_batch"][name]) == qpe.kernel_variants(name) + 1
+            assert all(m > 0 for m in res["ms_per_batch"][name])
         after = [P.cpu().numpy() for P in run()]
         for a, b in zip(after, before):
             assert np.array_equal(a, b)

@@ -126,6 +126,33 @@ def test_two_stream_schedule(qpe, form, flags):
         ctx.set_variant("batch_sched", 0)
 
 
+@pytest.mark.parametrize("flags", [0, 2], ids=["gate_route", "prefix_doubling"])
+def test_batch_wide_persistent(qpe, flags):
+    """The d = 256 controlled step of a batch on persistent workgroups
+    (batched controlled-step variant 3, with 512 or more tiles across three
+    instances) against the one-tile-per-workgroup schedule (variant 2, the
+    default) and against single runs, bit for bit, and against the Fejer
+    closed form."""
+    rng = np.random.default_rng(7700 + flags)
+    probs = [make_problem(n, 8, rng) for n in (16, 16, 15)] + [make_problem(11, 6, rng)]
+    say("persistent wide batch", flags)
+    items = [(dev(p.U), dev(p.psi), p.n_meas) for p in probs]
+    runner = qpe.Runner(items, form="mixed", flags=flags)
+    ctx = runner.ctx
+    out = {}
+    try:
+        for v in (2, 3):
+            ctx.set_variant("batch_ctrl", v)
+            out[v] = [host(P).copy() for P in runner()]
+    finally:
+        ctx.set_variant("batch_ctrl", 0)
+    for a, b in zip(out[2], out[3]):
+        assert np.array_equal(a, b)
+    for (U, psi, n), p, P in zip(items, probs, out[3]):
+        assert np.array_equal(host(qpe.run(U, psi, n, "mixed", flags=flags)), P)
+        assert float(np.abs(P - O.fejer(float(p.phis[0]), n)).max()) <= 1e-6
+
+
 def test_capture_first_run_of_a_fresh_context(qpe):
     """A batched run captured into a HIP graph as the very first call on a new
     context: the context already holds the second stream and its events, so
