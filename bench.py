@@ -50,7 +50,7 @@ EXECUTED = {"split_fp16x3": 3, "split_bf16x6": 6}
 # SHA-256 of the kernel source the counters were taken on. A changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    "e37aed1afeea1a22": {"fetch_bytes": 262307.4 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
+    "b0319bf79149ce9f": {"fetch_bytes": 262303.6 * 2.0 * 1024, "write_bytes": 262144.0 * 1024,
                          "profile": "profiles/ctrl_f16x3_qpe_n16_t10_hbm.md"},
 }
 CTRL_SRC = os.path.join(ROOT, "paper_2507_17175_amd", "csrc", "k_ctrl_mixed.hip")
