@@ -259,7 +259,11 @@ qpe_status qpe_controlled_step(qpe_ctx *ctx, int n_meas, int n_mat, int form, in
  * two stages of Fig. 1): state (N x d, complex128 for FP64, complex64 for
  * MIXED) is transformed in place into a digit-reversed row order (contents
  * unspecified afterwards) and prob[m] = sum_r |A[m, r]|^2 is written
- * (device float64 [N]). workspace >= qpe_iqft_workspace_size. */
+ * (device float64 [N]). workspace >= qpe_iqft_workspace_size: the twiddle
+ * tables and, for n_meas >= 12 except 17 (where the readout is summed
+ * inside the last DFT pass, from per-row partial sums over column groups),
+ * those partial sums. qpe_run and qpe_run_state take the same passes and
+ * sums, so all three return the same prob bit for bit. */
 qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size_t *bytes);
 qpe_status qpe_iqft_probs(qpe_ctx *ctx, int n_meas, int n_mat, int form, void *state,
                           double *prob, void *workspace, size_t workspace_bytes);

@@ -240,6 +240,16 @@ __device__ inline void prob_rows(const T* __restrict__ X, double* __restrict__ p
   if (c0 == 0 && p < N) prob[prob_index(p, n, plan)] = acc * scale;
 }
 
+// Readout after a fused last DFT pass: row p's partial sums, one per column
+// group, added in group order.
+__device__ inline void finish_row(const double* __restrict__ part, double* __restrict__ prob, int n, int groups,
+                                  const DftPlan& plan, double scale, int64_t p) {
+  const int64_t N = int64_t(1) << n;
+  double acc = 0.0;
+  for (int g = 0; g < groups; ++g) acc += part[g * N + p];
+  prob[prob_index(p, n, plan)] = acc * scale;
+}
+
 // Report: prob_sum, ||psi||^2, the input's peak weight, the defect and the
 // flags, by one block. With `part` (nparts pairs: partial sum, non-finite
 // flag, from k_report_partial) it adds the partial sums instead of reading
@@ -435,6 +445,13 @@ __global__ void __launch_bounds__(kThreads) k_prob(const T* __restrict__ X, doub
   const int64_t nwaves = (int64_t(gridDim.x) * kThreads) >> 6;
   for (int64_t base = wave * rows_per_wave; base < N; base += nwaves * rows_per_wave)
     prob_rows<T>(X, prob, n, t, plan, scale, base);
+}
+
+__global__ void __launch_bounds__(kThreads) k_prob_finish(const double* __restrict__ part, double* __restrict__ prob,
+                                                          int n, int groups, DftPlan plan, double scale) {
+  const int64_t N = int64_t(1) << n;
+  for (int64_t p = blockIdx.x * int64_t(kThreads) + threadIdx.x; p < N; p += int64_t(gridDim.x) * kThreads)
+    finish_row(part, prob, n, groups, plan, scale, p);
 }
 
 // Row position of outcome m after the DFT passes (the inverse of prob_index):
@@ -706,9 +723,19 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       state_scale_block(D.psi, n, t, reinterpret_cast<float*>(defect + kScratchSigma));
       break;
     case BK_PROB: {
+      const DftPlan plan = make_dft_plan(n);
+      if (fused_readout(n)) {
+        // the partials of the fused last pass, in the second state buffer
+        const double* part = reinterpret_cast<const double*>(D.ws + L.state1);
+        const int groups = readout_groups(mixed, n, t);
+        for (int r = 0; r < kProbRounds; ++r) {
+          const int64_t p = (local * kProbRounds + r) * kThreads + threadIdx.x;
+          if (p < (int64_t(1) << n)) finish_row(part, D.prob, n, groups, plan, ldexp(1.0, -n), p);
+        }
+        break;
+      }
       const int G = d < 64 ? d : 64;
       const int rows_per_wave = 64 / G;
-      const DftPlan plan = make_dft_plan(n);
       for (int r = 0; r < kProbRounds; ++r) {
         const int64_t base = ((local * kProbRounds + r) * 4 + (threadIdx.x >> 6)) * rows_per_wave;
         prob_rows<T>(reinterpret_cast<const T*>(D.ws + L.state0), D.prob, n, t, plan, ldexp(1.0, -n), base);
@@ -829,6 +856,14 @@ hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t
   else
     hipLaunchKernelGGL(k_prob<double2>, dim3(grid), dim3(kThreads), 0, s, static_cast<const double2*>(state), prob,
                        n, t, plan, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_prob_finish(const double* part, double* prob, int n, int groups, const DftPlan& plan,
+                              hipStream_t s) {
+  const int grid = grid_for(int64_t(1) << n);
+  hipLaunchKernelGGL(k_prob_finish, dim3(grid), dim3(kThreads), 0, s, part, prob, n, groups, plan,
+                     std::ldexp(1.0, -n));
   return hipGetLastError();
 }
 

@@ -16,6 +16,15 @@
 //
 // Twiddles exp(-2 pi i x / N) come from two small FP64 tables indexed by
 // the exact integer x (x = hi * 2^h + lo), multiplied in FP64.
+//
+// Fused readout (fused_readout(n): two passes or more, the last of 6-8
+// bits): the last pass does not store the transformed state (unless asked
+// to keep it) but forms |A|^2 of its outputs in FP64 and sums them over the
+// columns a workgroup holds, C = min(d, E) per row, with a fixed tree of
+// lane exchanges; it writes one partial per (column group, row) to
+// part[cg * N + p], and the readout sums the d / C partials of each row in
+// column-group order. This saves the readout's read of the state and the
+// last pass's write of it.
 #include "qpe_internal.hpp"
 
 namespace qpe {
@@ -103,6 +112,40 @@ __device__ __forceinline__ T twiddled(R yr, R yi, double2 w) {
   return o;
 }
 
+// Sums of v[0..R) over each aligned group of C consecutive lanes (C a power
+// of two, 1 <= C <= 64, the same in the whole wave) by recursive halving:
+// at lane offset o = C/2, C/4, ..., while a lane holds more than one value,
+// the lane with bit o set keeps the upper half of its values and sends the
+// lower half to its partner, which keeps the lower half, and each adds what
+// it received; once a single value is left, the remaining offsets are plain
+// exchange-and-add steps. On return the lane holds the group's sums for
+// j = first .. first + cnt - 1 in v[0..cnt); `owner` marks one lane per
+// distinct set of sums. The tree is fixed, so the sums are reproducible.
+template <int R>
+__device__ __forceinline__ void group_sums(double (&v)[R], int C, int lane, int& first, int& cnt, bool& owner) {
+  first = 0;
+  cnt = R;
+  int o = C >> 1;
+#pragma unroll
+  for (int h = R; h > 1; h >>= 1) {
+    if (o >= 1) {  // (uniform; no early exit, so the loop unrolls)
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < h / 2; ++i) {
+        const double keep = up ? v[h / 2 + i] : v[i];
+        const double send = up ? v[i] : v[h / 2 + i];
+        v[i] = keep + __shfl_xor(send, o);
+      }
+      if (up) first += h / 2;
+      cnt = h / 2;
+      o >>= 1;
+    }
+  }
+  const int rest = o;  // offsets left for the single value
+  for (; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o);
+  owner = rest == 0 || (lane & (2 * rest - 1)) == 0;
+}
+
 // Largest LDS exchange buffer of a pass with one DFT row per thread
 // (R1 = R2 = 16): 16 x 16 x 16 points.
 constexpr int kQftLds = 4096;
@@ -116,14 +159,19 @@ constexpr int kQftLds = 4096;
 // (R2 > 1 only): each thread takes EM of the R2 DFT rows of phase A, so a
 // workgroup covers E = EM kThreads / R2 consecutive elements and each row
 // access is EM times longer.
-template <typename T, int R1, int R2, int EM = 1>
+// FUSE: the last pass with the fused readout (part: the partials; keep: also
+// store the transformed state).
+template <typename T, int R1, int R2, int EM = 1, bool FUSE = false>
 __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restrict__ buf1, int gather, int n, int t,
                                          int pass_bits, int bits_before, const double2* __restrict__ tw_hi,
                                          const double2* __restrict__ tw_lo, int h, int64_t block,
-                                         T* __restrict__ L) {
+                                         T* __restrict__ L, double* __restrict__ part = nullptr,
+                                         bool keep = true) {
   typedef typename Real<T>::type R;
   static_assert(EM == 1 || R2 > 1, "the in-register pass takes one element per thread");
   constexpr int E = EM * kThreads / R2;  // elements per workgroup
+  static_assert(!FUSE || (R2 > 1 && E <= 64 && (E * R1) % kThreads == 0),
+                "fused readout: column groups within a wave, every lane in every round");
   // the grouped kernel's buffer holds EM kQftLds points
   static_assert(R1 * R2 * E <= EM * kQftLds, "LDS exchange buffer");
   constexpr int L1 = Log2<R1>::v, L2 = Log2<R2>::v;
@@ -213,12 +261,16 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
   if (R2 == 1) return;
   __syncthreads();
 
-  // Phase B: R2-point DFTs over j1b, outer twiddle, store.
+  // Phase B: R2-point DFTs over j1b, outer twiddle, store (or, fused, the
+  // column sums of |A|^2).
+  const int d = 1 << t;
+  const int C = d < E ? d : E;  // lanes (columns) that share a row
   for (int u = tid; u < E * R1; u += kThreads) {
     const int e = u % E, m1a = u / E;
-    if (f0 + e >= total_e) continue;
-    int64_t base, j2;
-    element(e, base, j2);
+    const bool ok = f0 + e < total_e;
+    if (!FUSE && !ok) continue;  // (fused: every lane takes part in the sums)
+    int64_t base = 0, j2 = 0;
+    if (ok) element(e, base, j2);
     R re[R2], im[R2];
 #pragma unroll
     for (int b = 0; b < R2; ++b) {
@@ -232,6 +284,7 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
     const double2 w0 = twiddle((j2 * m1a) << bits_before, tw_hi, tw_lo, h);
     const double2 ws = twiddle((j2 * R1) << bits_before, tw_hi, tw_lo, h);
     double2 w = w0;
+    double sq[R2];
 #pragma unroll
     for (int m1b = 0; m1b < R2; ++m1b) {
       const int m1 = m1a + R1 * m1b;
@@ -244,7 +297,27 @@ __device__ __forceinline__ void qft_tile(T* __restrict__ buf0, const T* __restri
       } else {
         o = twiddled<T, R>(yr, yi, w);
       }
-      buf0[base + int64_t(m1) * md] = o;
+      if (!FUSE || keep) {
+        if (ok) buf0[base + int64_t(m1) * md] = o;
+      }
+      if (FUSE) {
+        const double xr = double(o.x), xi = double(o.y);
+        sq[m1b] = ok ? xr * xr + xi * xi : 0.0;
+      }
+    }
+    if constexpr (FUSE) {
+      int first, cnt;
+      bool owner;
+      group_sums<R2>(sq, C, tid & 63, first, cnt, owner);
+      // row of output m1: (base >> t) + m1 2^m_log; column group col / C
+      const int64_t N = int64_t(1) << n;
+      const int64_t cg = (base & (d - 1)) / C;
+#pragma unroll
+      for (int j = 0; j < R2; ++j)
+        if (owner && ok && j < cnt) {
+          const int m1 = m1a + R1 * (first + j);
+          part[cg * N + (base >> t) + (int64_t(m1) << m_log)] = sq[j];
+        }
     }
   }
 }
@@ -256,6 +329,18 @@ __global__ void __launch_bounds__(kThreads) k_qft_pass(T* __restrict__ buf0, con
                                                        const double2* __restrict__ tw_lo, int h) {
   __shared__ T L[R2 > 1 ? R1 * R2 * (EM * kThreads / R2) : 1];
   qft_tile<T, R1, R2, EM>(buf0, buf1, gather, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, blockIdx.x, L);
+}
+
+// The last pass with the fused readout (no gather: a last pass of two or
+// more reads only buf0).
+template <typename T, int R1, int R2, int EM>
+__global__ void __launch_bounds__(kThreads) k_qft_last_fused(T* __restrict__ buf0, int n, int t, int pass_bits,
+                                                             int bits_before, const double2* __restrict__ tw_hi,
+                                                             const double2* __restrict__ tw_lo, int h,
+                                                             double* __restrict__ part, int keep) {
+  __shared__ T L[R1 * R2 * (EM * kThreads / R2)];
+  qft_tile<T, R1, R2, EM, true>(buf0, buf0, 0, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, blockIdx.x, L, part,
+                                keep != 0);
 }
 
 // Grouped pass `pass` over the instances of a launch table: each instance
@@ -299,6 +384,39 @@ __global__ void __launch_bounds__(kThreads) kb_qft(int pass, const InstDesc* __r
   }
 }
 
+// The fused last pass of the instances whose pass `pass` is their last
+// (launch kind BK_QFT_LAST): partials in the instance's second state buffer,
+// which no pass after the first reads.
+template <typename T, bool WIDE>
+__global__ void __launch_bounds__(kThreads) kb_qft_last(int pass, const InstDesc* __restrict__ desc,
+                                                        const int32_t* __restrict__ table, int bflags,
+                                                        int64_t tile0) {
+  constexpr bool mixed = sizeof(T) == 8;
+  __shared__ T L[WIDE ? 2 * kQftLds : kQftLds];
+  int64_t local;
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
+  const InstDesc D = load_desc(desc, i);
+  const RunLayout lay = run_layout(D.n, D.t, mixed, (bflags & kBatchPolar) != 0);
+  const DftPlan plan = make_dft_plan(D.n);
+  int before = 0;
+  for (int q = 0; q < pass; ++q) before += plan.bits[q];
+  T* b0 = reinterpret_cast<T*>(D.ws + lay.state0);
+  double* part = reinterpret_cast<double*>(D.ws + lay.state1);
+  const double2* hi = reinterpret_cast<const double2*>(D.ws + lay.tw_hi);
+  const double2* lo = reinterpret_cast<const double2*>(D.ws + lay.tw_lo);
+  const int h = tw_split(D.n), n = D.n, t = D.t;
+  switch (plan.bits[pass]) {
+    case 6: qft_tile<T, 16, 4, 1, true>(b0, b0, 0, n, t, 6, before, hi, lo, h, local, L, part, false); break;
+    case 7: qft_tile<T, 16, 8, 1, true>(b0, b0, 0, n, t, 7, before, hi, lo, h, local, L, part, false); break;
+    case 8:
+      if (WIDE && qft_two_rows(mixed, 8, n, t))
+        qft_tile<T, 16, 16, 2, true>(b0, b0, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
+      else
+        qft_tile<T, 16, 16, 1, true>(b0, b0, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
+      break;
+  }
+}
+
 template <typename T, int R1, int R2, int EM = 1>
 hipError_t go(void* b0, const void* b1, bool gather, int n, int t, int pb, int bb, const double2* hi,
               const double2* lo, int h, hipStream_t s) {
@@ -328,7 +446,38 @@ hipError_t dispatch(void* b0, const void* b1, bool gather, int n, int t, int pb,
   return hipErrorInvalidValue;
 }
 
+template <typename T, int R1, int R2, int EM = 1>
+hipError_t go_fused(void* b0, int n, int t, int pb, int bb, const double2* hi, const double2* lo, int h, double* part,
+                    bool keep, hipStream_t s) {
+  constexpr int E = EM * kThreads / R2;
+  int64_t total_e = int64_t(1) << (n + t - pb);
+  int64_t grid = (total_e + E - 1) / E;
+  hipLaunchKernelGGL((k_qft_last_fused<T, R1, R2, EM>), dim3(unsigned(grid)), dim3(kThreads), 0, s,
+                     static_cast<T*>(b0), n, t, pb, bb, hi, lo, h, part, keep ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_fused(void* b0, int n, int t, int pb, int bb, const double2* hi, const double2* lo, int h,
+                          double* part, bool keep, hipStream_t s) {
+  switch (pb) {
+    case 6: return go_fused<T, 16, 4>(b0, n, t, pb, bb, hi, lo, h, part, keep, s);
+    case 7: return go_fused<T, 16, 8>(b0, n, t, pb, bb, hi, lo, h, part, keep, s);
+    case 8:
+      if (qft_two_rows(sizeof(T) == 8, 8, n, t)) return go_fused<T, 16, 16, 2>(b0, n, t, pb, bb, hi, lo, h, part, keep, s);
+      return go_fused<T, 16, 16, 1>(b0, n, t, pb, bb, hi, lo, h, part, keep, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_qft_last_fused(bool mixed, void* buf0, int n, int t, int pass_bits, int bits_before,
+                                 const double2* tw_hi, const double2* tw_lo, int h, double* part, bool keep,
+                                 hipStream_t s) {
+  return mixed ? dispatch_fused<float2>(buf0, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, part, keep, s)
+               : dispatch_fused<double2>(buf0, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, part, keep, s);
+}
 
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
                             bool wide, int bflags, hipStream_t s) {
@@ -339,6 +488,18 @@ hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table
       hipLaunchKernelGGL((kb_qft<float2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
     else
       hipLaunchKernelGGL((kb_qft<double2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+  });
+}
+
+hipError_t launch_batch_qft_last(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                 bool wide, int bflags, hipStream_t s) {
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    if (mixed && wide)
+      hipLaunchKernelGGL((kb_qft_last<float2, true>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+    else if (mixed)
+      hipLaunchKernelGGL((kb_qft_last<float2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
+    else
+      hipLaunchKernelGGL((kb_qft_last<double2, false>), dim3(g), dim3(kThreads), 0, s, pass, desc, table, bflags, b);
   });
 }
 

@@ -23,7 +23,6 @@ namespace qpe {
 
 namespace {
 
-constexpr int kBK = 16;
 
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 
@@ -49,7 +48,7 @@ __device__ inline int2 xcd_tile_of(int w, int tiles_m, int tiles_n) {
   return make_int2(w / tiles_n, w % tiles_n);
 }
 
-template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN, int kBK = 16>
 __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs& g, int tile_m, int tile_n) {
   constexpr int kThreads = 64 * WM * WN;
   static_assert(WM * WN == 4 || WM * WN == 8, "4 or 8 waves");
@@ -276,7 +275,7 @@ __device__ inline void to_second_half(ZgemmArgs& a) {
   a.C = a.C2;
 }
 
-template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN, int BK>
 __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
   const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
   int w = blockIdx.x;
@@ -290,7 +289,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs 
     a.K /= 2;
   }
   const int2 tile = a.herm ? upper_tile(w, tiles_m) : xcd_tile_of(w, tiles_m, tiles_n);
-  zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN>(a, g, tile.x, tile.y);
+  zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN, BK>(a, g, tile.x, tile.y);
 }
 
 // ---- grouped (batched) forms: one launch over the instances of a table ----
@@ -396,7 +395,7 @@ __global__ void __launch_bounds__(256) kb_ctrl_f64(int step, const InstDesc* __r
   zgemm_tile<OP_N, OP_T, true, 64, 64, 2, 2>(a, g, int(local / tiles_n), int(local % tiles_n));
 }
 
-template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN>
+template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN, int BK = 16>
 hipError_t go(const ZgemmArgs& a_in, const GatherArgs& g, hipStream_t s) {
   ZgemmArgs a = a_in;
   // the Hermitian shortcut needs square tiles on a square product
@@ -404,27 +403,35 @@ hipError_t go(const ZgemmArgs& a_in, const GatherArgs& g, hipStream_t s) {
   const int T = (a.M + BM - 1) / BM;
   int tiles = a.herm ? T * (T + 1) / 2 : T * ((a.N + BN - 1) / BN);
   if (a.C2) tiles *= 2;  // both K halves
-  hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
+  hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN, BK>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
   return hipGetLastError();
 }
 
-// Tile variants of the power-chain GEMM: (BM, BN, waves).
-//   1: 32x32, 4 waves   2: 64x64, 4 waves   3: 64x64, 8 waves
-//   4: 128x64, 8 waves  5: 64x32, 4 waves
+// Tile variants of the power-chain GEMM: (BM, BN, waves, K slab).
+//   1: 32x32, 4 waves, 16   2: 64x64, 4 waves, 16   3: 64x64, 8 waves, 16
+//   4: 128x64, 8 waves, 16  5: 64x32, 4 waves, 16   6: 64x64, 8 waves, 32
+//   7: 32x32, 4 waves, 32
+// The K slab only groups the MFMA steps between barriers; every variant
+// accumulates each output over K in the same order.
 template <int OPA, int OPB>
 hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
   GatherArgs g{};
   if (variant == 0) {
     // Default (measured on MI355X): 64x64 tiles with 8 waves once there
-    // are >= 128 of them (d >= 1024: 7.2 ms per 15 squaring steps vs 7.9 ms
-    // for 32x32), 32x32 tiles below (d = 256: 1.34 ms vs 2.5 ms).
+    // are >= 128 of them (X = V V at d = 1024: 122-126 us against 144-152 us
+    // on 32x32 tiles; d = 2048: 829 vs 1019 us), 32x32 tiles below (d = 256:
+    // 15.0 us with 32-deep K slabs, 16.6 us with 16-deep, 31.6 us on 64x64).
     // A Hermitian product runs only the tiles on or above the diagonal, so
-    // it needs a larger grid before 64x64 tiles fill the chip.
+    // it needs a larger grid before 64x64 tiles fill the chip (X^H X at
+    // d = 1024: 107-111 us on 32x32 tiles in two K halves, 123 us on 64x64).
+    // The 32-deep slab halves the barriers of the small tiles; with K < 32
+    // it would only add zero steps.
     const int64_t t64 = (a.M + 63) / 64;
+    const int small = a.K >= 32 ? 7 : 1;
     if (a.herm && a.M == a.N)
-      variant = t64 * (t64 + 1) / 2 >= 256 ? 3 : 1;
+      variant = t64 * (t64 + 1) / 2 >= 256 ? 3 : small;
     else
-      variant = t64 * ((a.N + 63) / 64) >= 128 ? 3 : 1;
+      variant = t64 * ((a.N + 63) / 64) >= 128 ? 3 : small;
   }
   switch (variant) {
     case 1: return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);
@@ -432,13 +439,15 @@ hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
     case 3: return go<OPA, OPB, false, 64, 64, 4, 2>(a, g, s);
     case 4: return go<OPA, OPB, false, 128, 64, 4, 2>(a, g, s);
     case 5: return go<OPA, OPB, false, 64, 32, 2, 2>(a, g, s);
+    case 6: return go<OPA, OPB, false, 64, 64, 4, 2, 32>(a, g, s);
+    case 7: return go<OPA, OPB, false, 32, 32, 2, 2, 32>(a, g, s);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int zgemm_variants() { return 5; }
+int zgemm_variants() { return 7; }
 int ctrl_f64_variants() { return 2; }
 
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant) {

@@ -157,7 +157,10 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
       add(BK_CTRL_F64, k);
     }
   }
-  for (int q = 0; q < maxpass; ++q) add(BK_QFT, q);
+  for (int q = 0; q < maxpass; ++q) {
+    add(BK_QFT, q);
+    add(BK_QFT_LAST, q);
+  }
   add(BK_PROB, 0);
   if (with_report) add(BK_REPORT, 0);
   P.table_bytes = align_up(size_t(table_ints) * 4);
@@ -339,20 +342,34 @@ qpe_status controlled(qpe_ctx* ctx, bool mixed, int n, int t, int k, const doubl
   return QPE_OK;
 }
 
-qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, const void* s1, bool gather,
-                          double* prob, double2* tw_hi, double2* tw_lo) {
+// The inverse QFT passes and the readout. s1: the second state buffer (read
+// by the first pass when gather) or, with no gather, any buffer of at least
+// readout_groups(mixed, n, t) 2^n doubles distinct from s0; when the readout
+// is fused into the last pass (fused_readout(n)), its partial sums go to s1,
+// which the first pass has read by then. keep: leave the transformed state
+// in s0 (the fused last pass otherwise does not store it).
+qpe_status iqft_and_probs(qpe_ctx* ctx, bool mixed, int n, int t, void* s0, void* s1, bool gather, double* prob,
+                          double2* tw_hi, double2* tw_lo, bool keep = false) {
   hipStream_t s = ctx->stream;
   const int h = tw_split(n);
   QPE_HIP(ctx, launch_twiddles(tw_hi, tw_lo, n, h, s));
   DftPlan plan = make_dft_plan(n);
+  const bool fuse = fused_readout(n);
+  double* part = static_cast<double*>(s1);
   int before = 0;
   for (int q = 0; q < plan.npass; ++q) {
     TimerScope ts(ctx, QPE_TIMER_QFT);
-    QPE_HIP(ctx, launch_qft_pass(mixed, s0, s1, gather && q == 0, n, t, plan.bits[q], before, tw_hi, tw_lo, h, s));
+    if (fuse && q == plan.npass - 1)
+      QPE_HIP(ctx, launch_qft_last_fused(mixed, s0, n, t, plan.bits[q], before, tw_hi, tw_lo, h, part, keep, s));
+    else
+      QPE_HIP(ctx, launch_qft_pass(mixed, s0, s1, gather && q == 0, n, t, plan.bits[q], before, tw_hi, tw_lo, h, s));
     before += plan.bits[q];
   }
   TimerScope ts(ctx, QPE_TIMER_PROB);
-  QPE_HIP(ctx, launch_prob(mixed, s0, prob, n, t, plan, s));
+  if (fuse)
+    QPE_HIP(ctx, launch_prob_finish(part, prob, n, readout_groups(mixed, n, t), plan, s));
+  else
+    QPE_HIP(ctx, launch_prob(mixed, s0, prob, n, t, plan, s));
   return QPE_OK;
 }
 
@@ -369,7 +386,9 @@ qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* p
   return QPE_OK;
 }
 
-qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags, char* ws, qpe_report* report) {
+// keep_state: leave the final state (after the inverse QFT) in state0.
+qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags, char* ws, qpe_report* report,
+                   bool keep_state = false) {
   const int n = p.n_meas, t = p.n_mat, d = 1 << t;
   const bool mixed = form == QPE_FORM_MIXED;
   const bool polar = !(flags & QPE_NO_POLAR);
@@ -437,7 +456,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     if (st != QPE_OK) return st;
   }
   qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, !dbl, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
-                                 reinterpret_cast<double2*>(ws + L.tw_lo));
+                                 reinterpret_cast<double2*>(ws + L.tw_lo), keep_state);
   if (st != QPE_OK) return st;
   // the second state buffer is free once the inverse QFT has read it
   if (report)
@@ -462,7 +481,7 @@ int timer_of(int kind) {
     case BK_CTRL_SMALL: case BK_CTRL_M32: case BK_CTRL_M64: case BK_CTRL_M128: case BK_CTRL_M256:
     case BK_CTRL_F64:
       return QPE_TIMER_CTRL_GEMM;
-    case BK_QFT: return QPE_TIMER_QFT;
+    case BK_QFT: case BK_QFT_LAST: return QPE_TIMER_QFT;
     case BK_PROB: case BK_REPORT: return QPE_TIMER_PROB;
   }
   return -1;
@@ -637,13 +656,17 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_ROTU:
         QPE_HIP(ctx, launch_batch_rotate(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
         break;
-      case BK_QFT: {
+      case BK_QFT:
+      case BK_QFT_LAST: {
         bool wide = false;  // an instance takes two rows per thread in this pass
         for (int i = 0; i < count && !wide; ++i) {
           const DftPlan pl = make_dft_plan(p[i].n_meas);
           wide = L.step < pl.npass && qft_two_rows(mixed, pl.bits[L.step], p[i].n_meas, p[i].n_mat);
         }
-        QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, wide, bf, s));
+        if (L.kind == BK_QFT)
+          QPE_HIP(ctx, launch_batch_qft(L.step, desc, tab, tiles, mixed, wide, bf, s));
+        else
+          QPE_HIP(ctx, launch_batch_qft_last(L.step, desc, tab, tiles, mixed, wide, bf, s));
         break;
       }
       default:
@@ -1090,7 +1113,7 @@ QPE_API qpe_status qpe_run_state(qpe_ctx* ctx, const qpe_problem* problem, int f
   ctx->last_error.clear();
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
-  s = run_one(ctx, *problem, form, flags, static_cast<char*>(workspace), report);
+  s = run_one(ctx, *problem, form, flags, static_cast<char*>(workspace), report, true);
   if (s != QPE_OK) return s;
   const int n = problem->n_meas, t = problem->n_mat;
   const RunLayout L = run_layout(n, t, form, flags);
@@ -1192,6 +1215,7 @@ QPE_API qpe_status qpe_controlled_step(qpe_ctx* ctx, int n_meas, int n_mat, int 
   return QPE_OK;
 }
 
+// Twiddle tables, then (fused readout) the partial sums of the last pass.
 QPE_API qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size_t* bytes) {
   if (!bytes) return QPE_ERR_ARG;
   qpe_status s = check_sizes(n_meas, n_mat);
@@ -1199,6 +1223,8 @@ QPE_API qpe_status qpe_iqft_workspace_size(int n_meas, int n_mat, int form, size
   if (form != QPE_FORM_FP64 && form != QPE_FORM_MIXED) return QPE_ERR_ARG;
   const int h = tw_split(n_meas);
   *bytes = align_up((size_t(1) << (n_meas - h)) * 16) + align_up((size_t(1) << h) * 16);
+  if (fused_readout(n_meas))
+    *bytes += align_up((size_t(readout_groups(form == QPE_FORM_MIXED, n_meas, n_mat)) << n_meas) * 8);
   return QPE_OK;
 }
 
@@ -1216,9 +1242,11 @@ QPE_API qpe_status qpe_iqft_probs(qpe_ctx* ctx, int n_meas, int n_mat, int form,
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
   const int h = tw_split(n_meas);
   char* ws = static_cast<char*>(workspace);
+  const size_t hi_bytes = align_up((size_t(1) << (n_meas - h)) * 16), lo_bytes = align_up((size_t(1) << h) * 16);
   double2* tw_hi = reinterpret_cast<double2*>(ws);
-  double2* tw_lo = reinterpret_cast<double2*>(ws + align_up((size_t(1) << (n_meas - h)) * 16));
-  return iqft_and_probs(ctx, form == QPE_FORM_MIXED, n_meas, n_mat, state, nullptr, false, prob, tw_hi, tw_lo);
+  double2* tw_lo = reinterpret_cast<double2*>(ws + hi_bytes);
+  void* part = ws + hi_bytes + lo_bytes;  // used only with the fused readout
+  return iqft_and_probs(ctx, form == QPE_FORM_MIXED, n_meas, n_mat, state, part, false, prob, tw_hi, tw_lo);
 }
 
 // ------------------------------------------------------------- estimators

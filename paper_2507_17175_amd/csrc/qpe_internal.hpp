@@ -42,6 +42,31 @@ __host__ __device__ inline DftPlan make_dft_plan(int n) {
   return p;
 }
 
+// Elements (consecutive (row offset, column) pairs) per workgroup of a pass
+// of `bits` bits: 256 / R2 for the R1 x R2 split, twice that with two DFT
+// rows per thread.
+__host__ __device__ inline int qft_elems(bool mixed, int bits, int n, int t) {
+  const int r2 = bits > 4 ? (1 << (bits - 4)) : 1;
+  return (256 / r2) * (qft_two_rows(mixed, bits, n, t) ? 2 : 1);
+}
+
+// The readout is fused into the last DFT pass when there are two passes or
+// more (the last one then reads only the first state buffer, so the second
+// holds the partial sums) and the last pass has 6 to 8 bits (its workgroup
+// holds 16 to 64 elements, so the lanes of one row sit in one wave).
+__host__ __device__ inline bool fused_readout(int n) {
+  const DftPlan p = make_dft_plan(n);
+  return p.npass >= 2 && p.bits[p.npass - 1] >= 6;
+}
+
+// Partial sums per row of the fused readout: d / min(d, E) column groups for
+// the last pass's E; the partials take readout_groups * 2^n doubles.
+__host__ __device__ inline int readout_groups(bool mixed, int n, int t) {
+  const DftPlan p = make_dft_plan(n);
+  const int e = qft_elems(mixed, p.bits[p.npass - 1], n, t), d = 1 << t;
+  return d > e ? d / e : 1;
+}
+
 // Row position after the DFT passes -> outcome index m.
 // Digit q of p sits in bits [n - B_{q+1}, n - B_q) of p (B_q = bits[0] + ...
 // + bits[q-1]) and moves to bits [B_q, B_{q+1}) of m.
@@ -225,6 +250,7 @@ enum BatchKind {
   BK_QFT,
   BK_PROB,
   BK_REPORT,
+  BK_QFT_LAST,  // the last DFT pass of an instance with the fused readout
   BK_COUNT
 };
 
@@ -384,16 +410,18 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       return (mixed && t >= 8 && (bflags & kBatchF16) && step < n) ? cdiv(half, 128) * (d / 256) : 0;
     case BK_CTRL_F64:
       return (!mixed && t >= 5 && step < n) ? cdiv(half, 64) * cdiv(d, 64) : 0;
-    case BK_QFT: {
+    case BK_QFT:
+    case BK_QFT_LAST: {
       DftPlan pl = make_dft_plan(n);
       if (step >= pl.npass) return 0;
-      int b = pl.bits[step];
-      int r2 = b > 4 ? (1 << (b - 4)) : 1;
-      // elements per workgroup: 256 / r2, twice that with two rows per thread
-      int e = (256 / r2) * (qft_two_rows(mixed, b, n, t) ? 2 : 1);
-      return cdiv((N * d) >> b, e);
+      // the fused last pass runs in its own launch kind
+      if ((kind == BK_QFT_LAST) != (fused_readout(n) && step == pl.npass - 1)) return 0;
+      const int b = pl.bits[step];
+      return cdiv((N * d) >> b, qft_elems(mixed, b, n, t));
     }
     case BK_PROB: {
+      // fused readout: one row per thread; else rows of G lanes
+      if (fused_readout(n)) return cdiv(N, 256 * kProbRounds);
       int64_t G = d < 64 ? d : 64;
       return cdiv(N, 4 * (64 / G) * kProbRounds);
     }
@@ -485,6 +513,10 @@ hipError_t launch_unrotate_state(bool mixed, void* state, int n, int t, const un
                                  hipStream_t s);
 hipError_t launch_prob(bool mixed, const void* state, double* prob, int n, int t, const DftPlan& plan,
                        hipStream_t s);
+// The readout after a fused last pass: prob[m] = 2^-n sum_cg part[cg 2^n + p]
+// for the row p of outcome m, over the `groups` column groups in order.
+hipError_t launch_prob_finish(const double* part, double* prob, int n, int groups, const DftPlan& plan,
+                              hipStream_t s);
 // part (optional): device scratch of 2^n / 256 bytes (16-byte aligned) for
 // the partial sums of a two-stage sum when 2^n >= 16384.
 // rot_peak: the rotated input's peak weight (scratch word kScratchPeak) when
@@ -558,6 +590,12 @@ hipError_t launch_ctrl_small(bool mixed, void* buf0, void* buf1, const double2* 
 hipError_t launch_qft_pass(bool mixed, void* buf0, const void* buf1, bool gather, int n, int t,
                            int pass_bits, int bits_before, const double2* tw_hi, const double2* tw_lo,
                            int h, hipStream_t s);
+// The last pass with the fused readout (fused_readout(n)): reads buf0, writes
+// readout_groups(mixed, n, t) x 2^n partial sums to part (8-byte aligned,
+// distinct from buf0) and, with keep, the transformed state to buf0.
+hipError_t launch_qft_last_fused(bool mixed, void* buf0, int n, int t, int pass_bits, int bits_before,
+                                 const double2* tw_hi, const double2* tw_lo, int h, double* part, bool keep,
+                                 hipStream_t s);
 
 // ---- batched launchers: one grouped launch over the instances of a table ----
 struct BatchProblem {
@@ -595,5 +633,8 @@ hipError_t launch_batch_ctrl_small(int step, const InstDesc* desc, const int32_t
 // wide: some instance of the launch takes two rows per thread in this pass.
 hipError_t launch_batch_qft(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
                             bool wide, int bflags, hipStream_t s);
+// The same for the instances whose pass `pass` is their fused last pass.
+hipError_t launch_batch_qft_last(int pass, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                 bool wide, int bflags, hipStream_t s);
 
 }  // namespace qpe

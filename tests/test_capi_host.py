@@ -149,9 +149,10 @@ def test_autotune_and_variant_host_checks(L):
     assert L.qpe_ctx_get_variant(None, 0, 5, ctypes.byref(v)) == 1
     pb = _problems([(8, 5), (9, 7)])
     assert L.qpe_autotune_batch(None, pb, 2, 1, 0, 0x100000, 1 << 30, 2, chosen, None) == 1
-    # the batched classes: controlled step (three variants), power-chain
-    # tiles and schedule (two each)
-    for cls, nv in ((3, 3), (4, 2), (5, 2)):
+    # the controlled product (nine tile variants), the power-chain GEMM
+    # (seven), and the batched classes: controlled step (three variants),
+    # power-chain tiles and schedule (two each)
+    for cls, nv in ((0, 9), (1, 7), (3, 3), (4, 2), (5, 2)):
         c = ctypes.c_int()
         assert L.qpe_kernel_variants(cls, ctypes.byref(c)) == 0 and c.value == nv
     c = ctypes.c_int()
@@ -167,6 +168,18 @@ def test_stage_workspace_sizes(L):
     assert out.value >= (1 << 18) * 8
     assert L.qpe_iqft_workspace_size(20, 8, 1, ctypes.byref(out)) == 0
     assert L.qpe_iqft_workspace_size(0, 8, 1, ctypes.byref(out)) == 2
+    # the readout is summed inside the last DFT pass from n = 12 on (not at
+    # n = 17, whose last pass has 5 bits): the workspace then also holds the
+    # partial sums, one per row and column group of the last pass (32 columns
+    # per group for complex64 at n = 16, 16 for complex128)
+    sizes = {}
+    for n, t, form in ((11, 10, 1), (16, 10, 1), (16, 10, 0), (17, 10, 1)):
+        assert L.qpe_iqft_workspace_size(n, t, form, ctypes.byref(out)) == 0
+        sizes[n, form] = out.value
+    assert sizes[11, 1] < (1 << 11) * 8
+    assert sizes[16, 1] >= (1 << 16) * (1024 // 32) * 8
+    assert sizes[16, 0] >= (1 << 16) * (1024 // 16) * 8
+    assert sizes[17, 1] < (1 << 17) * 8
 
 
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
