@@ -345,7 +345,9 @@ enum {
                                 and 9 (the same, one persistent workgroup
                                 per CU; the default for d >= 256) exist
                                 for split FP16 only                   */
-  QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain          */
+  QPE_KERNEL_ZGEMM = 1,      /* FP64 GEMM of the power chain (the
+                                Gram products of n_mat = 10 and 11 run
+                                a fixed stream-K plan instead)        */
   QPE_KERNEL_CTRL_F64 = 2,   /* FP64 controlled GEMM (d >= 32)        */
   /* Batched runs (count > 1). One setting per context: n_mat is checked
    * but the choice applies to every instance size. */

@@ -192,18 +192,26 @@ __device__ inline void block_max_to(double mx, unsigned long long* __restrict__ 
   }
 }
 
+// The partial slots of a split Gram product (G2: the `extra` slots after
+// slot 0, d^2 apart) added to g in slot order.
+__device__ inline double2 add_gram_slots(double2 g, const double2* __restrict__ G2, int extra, int64_t dd, int64_t e) {
+  for (int sl = 0; sl < extra; ++sl) {
+    const double2 h = G2[sl * dd + e];
+    g.x += h.x;
+    g.y += h.y;
+  }
+  return g;
+}
+
 __device__ inline void subi_range(double2* __restrict__ G, const double2* __restrict__ G2, int d, int64_t e0,
                                   int64_t e1, int64_t stride, unsigned long long* __restrict__ defect_bits) {
   double mx = 0.0;
+  const int t = 31 - __builtin_clz(unsigned(d));
+  const int extra = G2 ? gram_extra_slots(t) : 0;
   for (int64_t e = e0; e < e1; e += stride) {
     double2 g = G[e];
     const bool diag = (e / d) == (e % d);
-    if (G2) {
-      // the two K halves of a split Gram product, added in a fixed order
-      const double2 h = G2[e];
-      g.x += h.x;
-      g.y += h.y;
-    }
+    if (G2) g = add_gram_slots(g, G2, extra, int64_t(d) * d, e);
     if (diag) g.x -= 1.0;
     if (G2 || diag) G[e] = g;
     mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
@@ -363,7 +371,7 @@ __device__ inline void ns_update_entry(const double2* __restrict__ X, const floa
 }
 
 
-// Mixed-form Newton-Schulz preparation in one pass: E = G (+ G2) - I with the
+// Mixed-form Newton-Schulz preparation in one pass: E = G (+ the slots in G2) - I with the
 // defect max |E_ij|, X32 = complex64(X), planes = split(conj(E)). E itself
 // is not stored (only its planes are used).
 __global__ void __launch_bounds__(kThreads) k_ns_prep_fused(const double2* __restrict__ X,
@@ -372,14 +380,11 @@ __global__ void __launch_bounds__(kThreads) k_ns_prep_fused(const double2* __res
                                                             uint16_t* __restrict__ planes, int t,
                                                             unsigned long long* __restrict__ defect_bits) {
   const int64_t d = int64_t(1) << t, dd = d * d;
+  const int extra = G2 ? gram_extra_slots(t) : 0;
   double mx = 0.0;
   for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
     double2 g = G[e];
-    if (G2) {
-      const double2 h = G2[e];
-      g.x += h.x;
-      g.y += h.y;
-    }
+    if (G2) g = add_gram_slots(g, G2, extra, dd, e);
     if ((e >> t) == (e & (d - 1))) g.x -= 1.0;
     mx = nan_max(mx, sqrt(g.x * g.x + g.y * g.y));
     const double2 x = X[e];

@@ -265,31 +265,62 @@ __device__ inline int2 upper_tile(int w, int T) {
   return make_int2(tm, tm + w);
 }
 
-// Second K half of a split product: the operands start K/2 further along K
-// and the result goes to C2.
-template <int OPA, int OPB>
-__device__ inline void to_second_half(ZgemmArgs& a) {
-  const int kh = a.K / 2;
-  a.A += OPA == OP_N ? int64_t(kh) : int64_t(kh) * a.lda;
-  a.B += OPB == OP_N ? int64_t(kh) * a.ldb : int64_t(kh);
-  a.C = a.C2;
-}
-
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN, int BK>
 __global__ void __launch_bounds__(64 * WM * WN) k_zgemm(ZgemmArgs a, GatherArgs g) {
   const int tiles_m = (a.M + BM - 1) / BM, tiles_n = (a.N + BN - 1) / BN;
-  int w = blockIdx.x;
-  if (a.C2) {
-    // split K: workgroups [0, tiles) take the first half, the rest the second
-    const int tiles = a.herm ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
-    if (w >= tiles) {
-      w -= tiles;
-      to_second_half<OPA, OPB>(a);
-    }
-    a.K /= 2;
-  }
-  const int2 tile = a.herm ? upper_tile(w, tiles_m) : xcd_tile_of(w, tiles_m, tiles_n);
+  const int2 tile = a.herm ? upper_tile(blockIdx.x, tiles_m) : xcd_tile_of(blockIdx.x, tiles_m, tiles_n);
   zgemm_tile<OPA, OPB, GATHER, BM, BN, WM, WN, BK>(a, g, tile.x, tile.y);
+}
+
+// Zeros over the 64 x 64 tile (tm, tn) of a d x d matrix and its mirror.
+template <int NT>
+__device__ inline void zero_tile64(double2* C, int d, int tm, int tn) {
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e >> 6, j = e & 63;
+    C[int64_t(tm * 64 + i) * d + tn * 64 + j] = make_double2(0.0, 0.0);
+    C[int64_t(tn * 64 + i) * d + tm * 64 + j] = make_double2(0.0, 0.0);
+  }
+}
+
+// Run `part` of the stream-K plan of G = X^H X (gram_split(t)): its slab
+// units, tile by tile, each tile's share added into the run's slot of that
+// tile (slot 0: G, slot s >= 1: G2 + (s - 1) d^2); the run that holds a
+// tile's last slab also clears the tile's slots beyond its own.
+template <int WM, int WN>
+__device__ void gram_run(const double2* X, double2* G, double2* G2, int t, int64_t part) {
+  const GramPlan P = gram_plan(t);
+  const int d = 1 << t;
+  const int64_t dd = int64_t(d) * d;
+  ZgemmArgs a{};
+  a.M = a.N = d;
+  a.lda = a.ldb = a.ldc = a.ldcin = d;
+  a.alpha = make_double2(1.0, 0.0);
+  a.beta = make_double2(0.0, 0.0);
+  a.herm = 1;
+  GatherArgs g{};
+  int64_t x = part * P.W;
+  const int64_t x1 = min(x + P.W, P.total);
+  while (x < x1) {
+    const int64_t u = x / P.nk;
+    const int k0 = int(x - u * P.nk);
+    const int k1 = int(min(int64_t(P.nk), k0 + (x1 - x)));
+    const int slot = int(part - u * P.nk / P.W);
+    const int2 tile = upper_tile(int(u), P.T);
+    // op(A) = X^H: element (k, i) is conj(X[k][i]); op(B) = X: (k, j) is X[k][j]
+    a.A = X + int64_t(k0) * 16 * d;
+    a.B = X + int64_t(k0) * 16 * d;
+    a.K = (k1 - k0) * 16;
+    a.C = slot == 0 ? G : G2 + (slot - 1) * dd;
+    zgemm_tile<OP_C, OP_N, false, 64, 64, WM, WN>(a, g, tile.x, tile.y);
+    if (k1 == P.nk)
+      for (int sl = slot + 1; sl < P.slots; ++sl) zero_tile64<64 * WM * WN>(G2 + (sl - 1) * dd, d, tile.x, tile.y);
+    x += k1 - k0;
+  }
+}
+
+__global__ void __launch_bounds__(512) k_gram_split(const double2* __restrict__ X, double2* __restrict__ G,
+                                                    double2* __restrict__ G2, int t) {
+  gram_run<4, 2>(X, G, G2, t, blockIdx.x);
 }
 
 // ---- grouped (batched) forms: one launch over the instances of a table ----
@@ -340,19 +371,7 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
   GatherArgs g{};
   if (KIND == BK_GRAM) {
     a.herm = 1;
-    int w = int(local);
-    if (gram_split(D.t)) {
-      // the two K halves as in the single-instance path: tiles [0, U) take
-      // the first half into gbuf, [U, 2U) the second into gbuf2
-      const int upper = tiles_n * (tiles_n + 1) / 2;
-      a.C2 = reinterpret_cast<double2*>(D.ws + L.gbuf2);
-      if (w >= upper) {
-        w -= upper;
-        to_second_half<OPA, OP_N>(a);
-      }
-      a.K /= 2;
-    }
-    const int2 tile = upper_tile(w, tiles_n);
+    const int2 tile = upper_tile(int(local), tiles_n);
     if constexpr (G64) {
       if (big) {
         zgemm_tile<OPA, OP_N, false, 64, 64, 2, 2>(a, g, tile.x, tile.y);
@@ -370,6 +389,19 @@ __global__ void __launch_bounds__(256) kb_zgemm(int step, const InstDesc* __rest
     zgemm_tile<OPA, OP_N, false, kBatchGemmTile, kBatchGemmTile, 2, 2>(a, g, int(local / tiles_n),
                                                                        int(local % tiles_n));
   }
+}
+
+// Gram products of step k by the stream-K plan (gram_split instances): run
+// `local` of the instance, with the single-instance path's workgroup shape.
+__global__ void __launch_bounds__(512) kb_gram_split(int step, const InstDesc* __restrict__ desc,
+                                                     const int32_t* __restrict__ table, int mixed, int bflags,
+                                                     int64_t tile0) {
+  int64_t local;
+  const int i = find_member(table, tile0 + blockIdx.x, &local);
+  const InstDesc D = load_desc(desc, i);
+  const RunLayout L = run_layout(D.n, D.t, mixed != 0, (bflags & kBatchPolar) != 0);
+  gram_run<4, 2>(reinterpret_cast<const double2*>(D.ws + L.vbuf), reinterpret_cast<double2*>(D.ws + L.gbuf),
+                 reinterpret_cast<double2*>(D.ws + L.gbuf2), D.t, local);
 }
 
 // FP64-form controlled step k with 64 x 64 tiles.
@@ -401,8 +433,7 @@ hipError_t go(const ZgemmArgs& a_in, const GatherArgs& g, hipStream_t s) {
   // the Hermitian shortcut needs square tiles on a square product
   if (a.herm && (BM != BN || a.M != a.N)) a.herm = 0;
   const int T = (a.M + BM - 1) / BM;
-  int tiles = a.herm ? T * (T + 1) / 2 : T * ((a.N + BN - 1) / BN);
-  if (a.C2) tiles *= 2;  // both K halves
+  const int tiles = a.herm ? T * (T + 1) / 2 : T * ((a.N + BN - 1) / BN);
   hipLaunchKernelGGL((k_zgemm<OPA, OPB, GATHER, BM, BN, WM, WN, BK>), dim3(tiles), dim3(64 * WM * WN), 0, s, a, g);
   return hipGetLastError();
 }
@@ -422,8 +453,8 @@ hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
     // on 32x32 tiles; d = 2048: 829 vs 1019 us), 32x32 tiles below (d = 256:
     // 15.0 us with 32-deep K slabs, 16.6 us with 16-deep, 31.6 us on 64x64).
     // A Hermitian product runs only the tiles on or above the diagonal, so
-    // it needs a larger grid before 64x64 tiles fill the chip (X^H X at
-    // d = 1024: 107-111 us on 32x32 tiles in two K halves, 123 us on 64x64).
+    // it needs a larger grid before 64x64 tiles fill the chip (the Gram
+    // products at d = 1024 and 2048 take the stream-K plan instead).
     // The 32-deep slab halves the barriers of the small tiles; with K < 32
     // it would only add zero steps.
     const int64_t t64 = (a.M + 63) / 64;
@@ -488,6 +519,18 @@ hipError_t launch_ctrl_f64(double2* buf0, double2* buf1, const double2* V, int n
     case 2: return go<OP_N, OP_T, true, 128, 64, 4, 2>(a, g, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_split(const double2* X, double2* G, double2* G2, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_split, dim3(gram_parts(t)), dim3(512), 0, s, X, G, G2, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gram_split(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                   int bflags, hipStream_t s) {
+  return for_grid_chunks(tiles, [&](unsigned g, int64_t b) {
+    hipLaunchKernelGGL(kb_gram_split, dim3(g), dim3(512), 0, s, step, desc, table, mixed ? 1 : 0, bflags, b);
+  });
 }
 
 hipError_t launch_batch_zgemm(int kind, int step, const InstDesc* desc, const int32_t* table, int64_t tiles,

@@ -135,6 +135,7 @@ BatchPlan plan_batch(const qpe_problem* p, int count, int form, unsigned flags, 
       add(BK_SQ, k);
       if (polar) {
         add(BK_GRAM, k);
+        add(BK_GRAM_SK, k);
         add(BK_SUBI, k);
         add(BK_CORR, k);
         add(BK_NSPREP, k);
@@ -291,21 +292,26 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   h.B = sq;
   h.C = g;
   h.herm = 1;
-  h.C2 = gram_split(tz) ? g2 : nullptr;  // two K halves into g and g2
-  QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));  // G = X^H X
+  // G = X^H X; at d = 1024 and 2048 by the stream-K plan, its partial
+  // slots in g and g2
+  if (gram_split(tz))
+    QPE_HIP(ctx, launch_gram_split(sq, g, g2, tz, s));
+  else
+    QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));
+  double2* gs = gram_split(tz) ? g2 : nullptr;
   if (planes && tz >= 5) {
     // E = G - I with the defect, X -> complex64 and the split of conj(E) in
     // one pass; after the product, the update also splits the new power
     // into the planes, which then hold the operator of the next step.
     float2* x32 = reinterpret_cast<float2*>(out);
     float2* xe = reinterpret_cast<float2*>(g);
-    QPE_HIP(ctx, launch_ns_prep_fused(sq, g, h.C2, x32, planes, tz, defect, s));
+    QPE_HIP(ctx, launch_ns_prep_fused(sq, g, gs, x32, planes, tz, defect, s));
     QPE_HIP(ctx, launch_ns_product(x32, xe, planes, tz, s));
     QPE_HIP(ctx, launch_ns_update_split(sq, xe, out, planes, tz, s, f16));
     if (planes_hold_out) *planes_hold_out = true;
     return QPE_OK;
   }
-  QPE_HIP(ctx, launch_sub_identity_defect(g, h.C2, d, defect, s));
+  QPE_HIP(ctx, launch_sub_identity_defect(g, gs, d, defect, s));
   ZgemmArgs c = a;
   c.A = sq;
   c.B = g;
@@ -474,7 +480,7 @@ int timer_of(int kind) {
   switch (kind) {
     case BK_HLAYER: return QPE_TIMER_HLAYER;
     case BK_ROTHASH: case BK_ROTPSI: case BK_ROTU: return QPE_TIMER_POWERS;
-    case BK_SQ: case BK_GRAM: case BK_SUBI: case BK_CORR:
+    case BK_SQ: case BK_GRAM: case BK_GRAM_SK: case BK_SUBI: case BK_CORR:
     case BK_NSPREP: case BK_NS_M32: case BK_NS_M64: case BK_NS_M128: case BK_NSUPD: case BK_PCOPY:
       return QPE_TIMER_POWERS;
     case BK_SPLIT: return QPE_TIMER_SPLIT;
@@ -501,7 +507,7 @@ int batch_variant_flags(const qpe_ctx* ctx) {
 // instance's square and Gram buffers, which no state-side launch touches:
 // they may run while the controlled products of step k-1 still read V_{k-1}
 // and the operator planes.
-bool chain_ahead(int kind) { return kind == BK_SQ || kind == BK_GRAM || kind == BK_SUBI; }
+bool chain_ahead(int kind) { return kind == BK_SQ || kind == BK_GRAM || kind == BK_GRAM_SK || kind == BK_SUBI; }
 // The rest of power step k: they write V_k's slot, the planes (the mixed
 // Newton-Schulz product stages conj(E) there) or the staging in it, so they
 // wait for the controlled products of step k-1.
@@ -635,6 +641,9 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
       case BK_GRAM:
       case BK_CORR:
         QPE_HIP(ctx, launch_batch_zgemm(L.kind, L.step, desc, tab, tiles, mixed, bf, s));
+        break;
+      case BK_GRAM_SK:
+        QPE_HIP(ctx, launch_batch_gram_split(L.step, desc, tab, tiles, mixed, bf, s));
         break;
       case BK_CTRL_SMALL:
         QPE_HIP(ctx, launch_batch_ctrl_small(L.step, desc, tab, tiles, mixed, stage_small, bf, s));
@@ -1136,7 +1145,7 @@ QPE_API qpe_status qpe_powers_workspace_size(int n_mat, size_t* bytes) {
   if (!bytes) return QPE_ERR_ARG;
   if (n_mat < 0 || n_mat > QPE_MAX_N_MAT) return QPE_ERR_SIZE;
   size_t mat = (size_t(1) << (2 * n_mat)) * 16;
-  *bytes = (gram_split(n_mat) ? 3 : 2) * align_up(mat) + align_up(64);
+  *bytes = (2 + gram_extra_slots(n_mat)) * align_up(mat) + align_up(64);
   return QPE_OK;
 }
 
@@ -1160,7 +1169,7 @@ QPE_API qpe_status qpe_powers(qpe_ctx* ctx, int n_mat, const void* U, int count_
   double2* g = reinterpret_cast<double2*>(ws + align_up(mat * 16));
   double2* g2 = gram_split(n_mat) ? reinterpret_cast<double2*>(ws + 2 * align_up(mat * 16)) : nullptr;
   unsigned long long* defect =
-      reinterpret_cast<unsigned long long*>(ws + (gram_split(n_mat) ? 3 : 2) * align_up(mat * 16));
+      reinterpret_cast<unsigned long long*>(ws + (2 + gram_extra_slots(n_mat)) * align_up(mat * 16));
   double2* V = static_cast<double2*>(V_out);
   const bool polar = !(flags & QPE_NO_POLAR);
   QPE_HIP(ctx, launch_zero_u64(defect, 1, ctx->stream));

@@ -119,13 +119,42 @@ __host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) /
 __host__ __device__ inline int tw_split(int n) { return (n + 1) / 2; }
 
 // The Gram product X^H X of the Newton-Schulz step computes only its upper
-// tiles. At d = 1024 and 2048 their count (528 tiles of 32 x 32, or of
-// 64 x 64) leaves the 256 CUs unevenly loaded (two or three workgroups
-// each), so the product is split in two K halves (each tile twice) whose
-// partial sums go to gbuf and gbuf2 and are added, in that order, by the
-// identity subtraction (measured at d = 1024: 137 us -> 108 us). The batched
-// path splits at the same sizes, so both paths add the same partial sums.
+// tiles. At d = 1024 and 2048 their count (136 or 528 tiles of 64 x 64)
+// leaves the 256 CUs unevenly loaded, so the product runs stream-K: the
+// (upper tile, 16-deep K slab) units, tile by tile, are cut into
+// gram_parts(t) equal runs of consecutive units, one workgroup each. A run adds
+// its slabs of one tile into a partial "slot" (the number of runs that
+// started in that tile before it); slot 0 is gbuf, slots 1.. follow each
+// other in gbuf2, and the identity subtraction adds them in slot order. The
+// tile's last run clears the slots no run of it reached. The plan depends
+// on d only, so the batched path, which follows it too, adds the same
+// partial sums.
 __host__ __device__ inline bool gram_split(int t) { return t == 10 || t == 11; }
+// Runs (workgroups) of the plan: two per CU, so that one covers the other's
+// barriers (measured on MI355X, with the slot sums of the identity
+// subtraction: d = 1024: 82 + 25 us against 91 + 21 us with 256 runs and
+// 107-111 + 18 us for 32 x 32 tiles in two K halves; d = 2048: 491 + 36 us
+// against 595 + 36 us with 256 runs and 571 us in two K halves).
+__host__ __device__ inline int gram_parts(int) { return 512; }
+struct GramPlan {
+  int T, nk;       // upper tiles per side (d / 64), slabs per tile (d / 16)
+  int64_t total, W;  // units, units per run
+  int slots;       // partial slots (the most runs any tile meets)
+};
+__host__ __device__ inline GramPlan gram_plan(int t) {
+  GramPlan g;
+  const int d = 1 << t;
+  g.T = d / 64;
+  g.nk = d / 16;
+  g.total = int64_t(g.T) * (g.T + 1) / 2 * g.nk;
+  g.W = (g.total + gram_parts(t) - 1) / gram_parts(t);
+  // a tile's units [u nk, u nk + nk) meet runs floor(u nk / W) ..
+  // floor((u nk + nk - 1) / W): at most ceil((nk - 1) / W) + 1 of them
+  g.slots = int((g.nk - 1 + g.W - 1) / g.W) + 1;
+  return g;
+}
+// Matrices of partial sums in gbuf2 (0 when the Gram product is not split).
+__host__ __device__ inline int gram_extra_slots(int t) { return gram_split(t) ? gram_plan(t).slots - 1 : 0; }
 
 // The instance's small scratch region holds, as 8-byte words: the unitarity
 // defect (the bits of a non-negative double, atomically maxed), the key of the
@@ -164,7 +193,7 @@ __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool p
   L.gbuf = off;
   if (polar) off = align_up(off + mat);
   L.gbuf2 = off;
-  if (polar && gram_split(t)) off = align_up(off + mat);
+  if (polar) off = align_up(off + gram_extra_slots(t) * mat);
   L.planes = off;
   if (mixed && t >= 5) off = align_up(off + 6 * d * d * 2);
   const int h = tw_split(n);
@@ -251,6 +280,7 @@ enum BatchKind {
   BK_PROB,
   BK_REPORT,
   BK_QFT_LAST,  // the last DFT pass of an instance with the fused readout
+  BK_GRAM_SK,   // the Gram product of d = 1024 and 2048 (stream-K runs)
   BK_COUNT
 };
 
@@ -375,10 +405,12 @@ __host__ __device__ inline int64_t batch_tiles(int kind, int step, int n, int t,
       return (step >= 1 && step < n) ? T * T : 0;
     }
     case BK_GRAM: {
-      // Hermitian: the tiles on or above the diagonal (twice when split)
+      // Hermitian: the tiles on or above the diagonal
       const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
-      return (ns && step < n) ? T * (T + 1) / 2 * (gram_split(t) ? 2 : 1) : 0;
+      return (ns && step < n && !gram_split(t)) ? T * (T + 1) / 2 : 0;
     }
+    case BK_GRAM_SK:  // the runs of the stream-K plan
+      return (ns && step < n && gram_split(t)) ? int64_t(gram_parts(t)) : 0;
     case BK_CORR: {
       const int64_t T = cdiv(d, batch_gemm_tile(t, bflags));
       return (ns && !(mixed && t >= 5) && step < n) ? T * T : 0;
@@ -556,12 +588,15 @@ struct ZgemmArgs {
   // Hermitian result (op(A) = B^H, alpha real, beta 0): only tiles on or
   // above the diagonal are computed; each mirrors itself below it.
   int herm;
-  // K split in two halves (beta 0): the first half's product goes to C, the
-  // second's to C2 (both M x N with ldc); the caller adds them.
-  double2* C2;
 };
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant);
 int zgemm_variants();
+// The split Gram product (gram_split(t)) by the stream-K plan: slot 0 of
+// G = X^H X in G, slots 1.. in G2 (d x d each, consecutive).
+hipError_t launch_gram_split(const double2* X, double2* G, double2* G2, int t, hipStream_t s);
+// The same for the instances of a launch table (kind BK_GRAM_SK, step k).
+hipError_t launch_batch_gram_split(int step, const InstDesc* desc, const int32_t* table, int64_t tiles, bool mixed,
+                                   int bflags, hipStream_t s);
 
 // Controlled step k, FP64 form: rows j with bit k set, read from
 // buf[row_parity(j,k)], written to the other buffer: s <- V s.

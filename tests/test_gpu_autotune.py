@@ -47,7 +47,7 @@ def test_autotune_keeps_results(qpe, form, n, t):
 
 def _batch_items(seed):
     # uneven sizes on both sides of the d >= 64 tile switch and of the d >= 128
-    # controlled-step class, and one d = 1024 instance (Gram split in K halves)
+    # controlled-step class, and one d = 1024 instance (stream-K Gram product)
     shapes = [(9, 3), (10, 6), (8, 7), (11, 8), (7, 5), (12, 6), (9, 8), (6, 10)]
     rng = np.random.default_rng(seed)
     probs = [make_problem(n, t, rng) for n, t in shapes]

@@ -67,7 +67,8 @@ def test_zgemm(qpe, opA, opB, m, n, k):
 
 # ----------------------------------------------------------------- powers
 
-@pytest.mark.parametrize("t,count", [(2, 8), (5, 12), (8, 16), (10, 16)])
+# d = 1024 and 2048 take the stream-K Gram product (partial slots)
+@pytest.mark.parametrize("t,count", [(2, 8), (5, 12), (8, 16), (10, 16), (11, 8)])
 def test_powers_vs_spectral(qpe, t, count):
     say("powers", "t", t, "count", count)
     rng = np.random.default_rng(100 + t)
