@@ -20,62 +20,101 @@ template <typename T> struct Real;
 template <> struct Real<float2> { typedef float type; };
 template <> struct Real<double2> { typedef double type; };
 
-// Gathered rows [i0, min(i0 + kThreads, M)) of step k: thread r computes row
-// i0 + r from LDS; the tile moves in and out with element e = tid + q
-// kThreads (row e / D, amplitude e % D), rows padded to D + 1 amplitudes.
+// The D amplitudes a thread moves of the gathered rows [i0, i0 + kThreads)
+// of step k: element e = tid + q kThreads (row e / D, amplitude e % D), so
+// that consecutive lanes read consecutive amplitudes.
 template <typename T, int D>
-__device__ __forceinline__ void ctrl_small_tile(T* __restrict__ buf0, T* __restrict__ buf1, const T* __restrict__ Vs,
-                                                int k, uint64_t pmask, int64_t i0, int64_t M, T* __restrict__ X) {
+__device__ __forceinline__ void load_tile_regs(const T* __restrict__ buf0, const T* __restrict__ buf1, int k,
+                                               uint64_t pmask, int64_t i0, int64_t M, T (&r)[D]) {
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
+    const int64_t i = i0 + row;
+    if (i < M) {
+      const int64_t j = step_row(i, k, pmask);
+      r[q] = ((src_buffer(j, pmask) ? buf1 : buf0) + j * D)[c];
+    }
+  }
+}
+
+// Gathered rows of step k in tiles of kThreads: tiles b = tile0, tile0 +
+// stride, ... below tile_end. Each tile goes HBM -> registers -> LDS (X,
+// rows padded to D + 1 amplitudes); thread r then computes row r from LDS;
+// the result goes back through LDS to the other ping-pong buffer. For
+// complex64 the next tile's loads are issued before the current tile is
+// computed (complex128 rows would not fit in registers beside the row being
+// computed).
+template <typename T, int D>
+__device__ __forceinline__ void ctrl_small_tiles(T* __restrict__ buf0, T* __restrict__ buf1, const T* __restrict__ Vs,
+                                                 int k, uint64_t pmask, int64_t tile0, int64_t tile_end,
+                                                 int64_t stride, int64_t M, T* __restrict__ X) {
   typedef typename Real<T>::type R;
   constexpr int P = D + 1;
+  constexpr bool kAhead = sizeof(T) == 8;
+  T rv[kAhead ? D : 1];
+  int64_t b = tile0;
+  if constexpr (kAhead)
+    if (b < tile_end && b * kThreads < M) load_tile_regs<T, D>(buf0, buf1, k, pmask, b * kThreads, M, rv);
+  for (; b < tile_end && b * kThreads < M; b += stride) {
+    const int64_t i0 = b * kThreads;
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
-    const int64_t i = i0 + row;
-    if (i < M) {
-      const int64_t j = step_row(i, k, pmask);
-      X[row * P + c] = ((src_buffer(j, pmask) ? buf1 : buf0) + j * D)[c];
+    for (int q = 0; q < D; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      const int64_t i = i0 + e / D;
+      if (i < M) {
+        if constexpr (kAhead) {
+          X[(e / D) * P + e % D] = rv[q];
+        } else {
+          const int64_t j = step_row(i, k, pmask);
+          X[(e / D) * P + e % D] = ((src_buffer(j, pmask) ? buf1 : buf0) + j * D)[e % D];
+        }
+      }
     }
-  }
-  __syncthreads();
-  if (i0 + threadIdx.x < M) {
-    T* x = X + threadIdx.x * P;
-    R xr[D], xi[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      const T v = x[c];
-      xr[c] = v.x;
-      xi[c] = v.y;
+    __syncthreads();
+    if constexpr (kAhead) {
+      const int64_t nb = b + stride;
+      if (nb < tile_end && nb * kThreads < M) load_tile_regs<T, D>(buf0, buf1, k, pmask, nb * kThreads, M, rv);
     }
-    // Rolled: unrolling lets the compiler hoist all d*d operator entries
-    // out of the row loop into registers, which spills.
-#pragma unroll 1
-    for (int r = 0; r < D; ++r) {
-      R yr = R(0), yi = R(0);
+    if (i0 + threadIdx.x < M) {
+      T* x = X + threadIdx.x * P;
+      R xr[D], xi[D];
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const T v = Vs[r * D + c];
-        const R vr = v.x, vi = v.y;
-        yr = fma(vr, xr[c], yr);
-        yr = fma(-vi, xi[c], yr);
-        yi = fma(vr, xi[c], yi);
-        yi = fma(vi, xr[c], yi);
+        const T v = x[c];
+        xr[c] = v.x;
+        xi[c] = v.y;
       }
-      T o;
-      o.x = yr;
-      o.y = yi;
-      x[r] = o;
-    }
-  }
-  __syncthreads();
+      // Rolled: unrolling lets the compiler hoist all d*d operator entries
+      // out of the row loop into registers, which spills.
+#pragma unroll 1
+      for (int r = 0; r < D; ++r) {
+        R yr = R(0), yi = R(0);
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
-    const int64_t i = i0 + row;
-    if (i < M) {
-      const int64_t j = step_row(i, k, pmask);
-      ((src_buffer(j, pmask) ? buf0 : buf1) + j * D)[c] = X[row * P + c];
+        for (int c = 0; c < D; ++c) {
+          const T v = Vs[r * D + c];
+          const R vr = v.x, vi = v.y;
+          yr = fma(vr, xr[c], yr);
+          yr = fma(-vi, xi[c], yr);
+          yi = fma(vr, xi[c], yi);
+          yi = fma(vi, xr[c], yi);
+        }
+        T o;
+        o.x = yr;
+        o.y = yi;
+        x[r] = o;
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const int e = threadIdx.x + q * kThreads, row = e / D, c = e % D;
+      const int64_t i = i0 + row;
+      if (i < M) {
+        const int64_t j = step_row(i, k, pmask);
+        ((src_buffer(j, pmask) ? buf0 : buf1) + j * D)[c] = X[row * P + c];
+      }
+    }
+    __syncthreads();  // X is staged again for the next tile
   }
 }
 
@@ -92,24 +131,25 @@ __device__ __forceinline__ void load_operator(const double2* __restrict__ V, T* 
   __syncthreads();
 }
 
-// Rows [0, M) in tiles of kThreads, tile b, b + stride, ...; Vs is LDS of
-// D * D elements. With STAGE and D >= 8 the rows go through X (LDS of
-// kThreads * (D + 1) elements); otherwise each thread reads and writes its own
-// row directly, which costs less for rows of at most four amplitudes (32 or
-// 64 bytes), where the LDS round trip saves nothing.
+// Rows [0, M) in tiles of kThreads: tiles b = tile0, tile0 + stride, ...
+// below tile_end; Vs is LDS of D * D elements. With STAGE and D >= 8 the
+// rows go through X (LDS of kThreads * (D + 1) elements); otherwise each
+// thread reads and writes its own row directly, which costs less for rows of
+// at most four amplitudes (32 or 64 bytes), where the LDS round trip saves
+// nothing.
 template <typename T, int D, bool STAGE>
 __device__ __forceinline__ void ctrl_small_rows(T* __restrict__ buf0, T* __restrict__ buf1,
                                                 const double2* __restrict__ V, int k, uint64_t pmask, int64_t tile0,
-                                                int64_t M, int64_t stride, T* __restrict__ Vs, T* __restrict__ X) {
+                                                int64_t tile_end, int64_t M, int64_t stride, T* __restrict__ Vs,
+                                                T* __restrict__ X) {
   load_operator<T, D>(V, Vs);
   if constexpr (STAGE && D >= 8) {
-    for (int64_t b = tile0; b * kThreads < M; b += stride) {
-      ctrl_small_tile<T, D>(buf0, buf1, Vs, k, pmask, b * kThreads, M, X);
-      __syncthreads();
-    }
+    ctrl_small_tiles<T, D>(buf0, buf1, Vs, k, pmask, tile0, tile_end, stride, M, X);
   } else {
     typedef typename Real<T>::type R;
-    for (int64_t i = tile0 * kThreads + threadIdx.x; i < M; i += stride * kThreads) {
+    for (int64_t b = tile0; b < tile_end && b * kThreads < M; b += stride) {
+      const int64_t i = b * kThreads + threadIdx.x;
+      if (i >= M) break;
       const int64_t j = step_row(i, k, pmask);
       const int p = src_buffer(j, pmask);
       const T* src = (p ? buf1 : buf0) + j * D;
@@ -150,11 +190,11 @@ __global__ void __launch_bounds__(kThreads) k_ctrl_small(T* __restrict__ buf0, T
   __shared__ T Vs[D * D];
   __shared__ T X[D >= 8 ? kThreads * (D + 1) : 1];
   const int64_t M = int64_t(1) << (n - 1);
-  ctrl_small_rows<T, D, true>(buf0, buf1, V, k, pmask, blockIdx.x, M, gridDim.x, Vs, X);
+  ctrl_small_rows<T, D, true>(buf0, buf1, V, k, pmask, blockIdx.x, INT64_MAX, M, gridDim.x, Vs, X);
 }
 
 // Grouped controlled step k over the d <= 16 instances of a launch table:
-// 256 gathered rows per workgroup. STAGE (LDS staging for d = 8, 16) is
+// kSmallTiles tiles of 256 gathered rows per workgroup. STAGE (LDS staging for d = 8, 16) is
 // launched only when such instances take part: its LDS tile would otherwise
 // only lower the occupancy of the d <= 4 rows.
 template <typename T, bool STAGE>
@@ -174,22 +214,22 @@ __global__ void __launch_bounds__(kThreads) kb_ctrl_small(int step, const InstDe
   T* b1 = dbl ? b0 + (int64_t(1) << step) * (int64_t(1) << D.t) : reinterpret_cast<T*>(D.ws + L.state1);
   const uint64_t pmask = dbl ? kDoubling : (uint64_t(1) << step) - 1;
   const int64_t M = int64_t(1) << (dbl ? step : D.n - 1);
-  constexpr int64_t kOnce = int64_t(1) << 40;  // one tile per workgroup
+  const int64_t t0 = local * kSmallTiles, t1 = t0 + kSmallTiles;
   __shared__ T Vs[16 * 16];
   __shared__ T X[STAGE ? kThreads * 17 : 1];
   switch (D.t) {
-    case 0: ctrl_small_rows<T, 1, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
-    case 1: ctrl_small_rows<T, 2, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
-    case 2: ctrl_small_rows<T, 4, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
-    case 3: ctrl_small_rows<T, 8, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
-    case 4: ctrl_small_rows<T, 16, STAGE>(b0, b1, V, step, pmask, local, M, kOnce, Vs, X); break;
+    case 0: ctrl_small_rows<T, 1, STAGE>(b0, b1, V, step, pmask, t0, t1, M, 1, Vs, X); break;
+    case 1: ctrl_small_rows<T, 2, STAGE>(b0, b1, V, step, pmask, t0, t1, M, 1, Vs, X); break;
+    case 2: ctrl_small_rows<T, 4, STAGE>(b0, b1, V, step, pmask, t0, t1, M, 1, Vs, X); break;
+    case 3: ctrl_small_rows<T, 8, STAGE>(b0, b1, V, step, pmask, t0, t1, M, 1, Vs, X); break;
+    case 4: ctrl_small_rows<T, 16, STAGE>(b0, b1, V, step, pmask, t0, t1, M, 1, Vs, X); break;
   }
 }
 
 template <typename T, int D>
 hipError_t go(void* b0, void* b1, const double2* V, int n, int k, uint64_t pmask, hipStream_t s) {
   int64_t M = int64_t(1) << (n - 1);
-  int64_t g = (M + kThreads - 1) / kThreads;
+  int64_t g = (M + kThreads * kSmallTiles - 1) / (kThreads * kSmallTiles);
   if (g > 256 * 32) g = 256 * 32;
   hipLaunchKernelGGL((k_ctrl_small<T, D>), dim3(int(g)), dim3(kThreads), 0, s, static_cast<T*>(b0),
                      static_cast<T*>(b1), V, n, k, pmask);
