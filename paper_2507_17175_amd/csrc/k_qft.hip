@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kThreads) k_qft_last_fused(T* __restrict__ buf
                                                              const double2* __restrict__ tw_lo, int h,
                                                              double* __restrict__ part, int keep) {
   __shared__ T L[R1 * R2 * (EM * kThreads / R2)];
-  qft_tile<T, R1, R2, EM, true>(buf0, buf0, 0, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, blockIdx.x, L, part,
+  qft_tile<T, R1, R2, EM, true>(buf0, nullptr, 0, n, t, pass_bits, bits_before, tw_hi, tw_lo, h, blockIdx.x, L, part,
                                 keep != 0);
 }
 
@@ -406,13 +406,13 @@ __global__ void __launch_bounds__(kThreads) kb_qft_last(int pass, const InstDesc
   const double2* lo = reinterpret_cast<const double2*>(D.ws + lay.tw_lo);
   const int h = tw_split(D.n), n = D.n, t = D.t;
   switch (plan.bits[pass]) {
-    case 6: qft_tile<T, 16, 4, 1, true>(b0, b0, 0, n, t, 6, before, hi, lo, h, local, L, part, false); break;
-    case 7: qft_tile<T, 16, 8, 1, true>(b0, b0, 0, n, t, 7, before, hi, lo, h, local, L, part, false); break;
+    case 6: qft_tile<T, 16, 4, 1, true>(b0, nullptr, 0, n, t, 6, before, hi, lo, h, local, L, part, false); break;
+    case 7: qft_tile<T, 16, 8, 1, true>(b0, nullptr, 0, n, t, 7, before, hi, lo, h, local, L, part, false); break;
     case 8:
       if (WIDE && qft_two_rows(mixed, 8, n, t))
-        qft_tile<T, 16, 16, 2, true>(b0, b0, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
+        qft_tile<T, 16, 16, 2, true>(b0, nullptr, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
       else
-        qft_tile<T, 16, 16, 1, true>(b0, b0, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
+        qft_tile<T, 16, 16, 1, true>(b0, nullptr, 0, n, t, 8, before, hi, lo, h, local, L, part, false);
       break;
   }
 }
