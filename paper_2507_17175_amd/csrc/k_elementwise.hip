@@ -113,8 +113,9 @@ __device__ inline void split_value(double2 v, uint16_t* __restrict__ planes, int
 __device__ inline double f16_round(double x) {
   const double a = fabs(x);
   if (a < 0x1p-14) return rint(x * 0x1p24) * 0x1p-24;
-  const double q = ldexp(1.0, ilogb(a) - 10);
-  return rint(x / q) * q;
+  const int e = ilogb(a);
+  // x / q with q = 2^(e - 10), as an exact product by 2^(10 - e)
+  return rint(x * ldexp(1.0, 10 - e)) * ldexp(1.0, e - 10);
 }
 
 __device__ inline uint16_t f16_bits(double exact_f16) {
@@ -138,6 +139,32 @@ __device__ inline void split_value_f16(double2 v, uint16_t* __restrict__ planes,
     planes[(0 * 2 + comp) * dd + dst] = f16_bits(hi);
     planes[(1 * 2 + comp) * dd + dst] = f16_bits(lo);
   }
+}
+
+// The same for the four columns c .. c+3 (c a multiple of 4, d >= 4) of one
+// row, starting at element e0: they share a 16-column block, so each plane
+// takes their four pieces as one 8-byte store.
+__device__ inline void split4_f16(const double2 (&v)[4], uint16_t* __restrict__ planes, int t, int64_t e0) {
+  const int64_t d = int64_t(1) << t;
+  const int64_t dd = d * d;
+  const int64_t j = e0 >> t, c = e0 & (d - 1);
+  const int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
+  uint16_t p[4][4];  // [plane][column]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double w[2] = {v[i].x * kOpScaleF16, v[i].y * kOpScaleF16};
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      const double hi = f16_round(w[comp]);
+      const double lo = f16_round(w[comp] - hi);
+      p[comp][i] = f16_bits(hi);
+      p[2 + comp][i] = f16_bits(lo);
+    }
+  }
+#pragma unroll
+  for (int pl = 0; pl < 4; ++pl)
+    *reinterpret_cast<uint2*>(planes + pl * dd + dst) =
+        make_uint2(uint32_t(p[pl][0]) | (uint32_t(p[pl][1]) << 16), uint32_t(p[pl][2]) | (uint32_t(p[pl][3]) << 16));
 }
 
 __device__ inline void split_entry(const double2* __restrict__ V, uint16_t* __restrict__ planes, int t, int64_t e,
@@ -402,15 +429,28 @@ __global__ void __launch_bounds__(kThreads) k_ns_update_split(const double2* __r
                                                               double2* __restrict__ out,
                                                               uint16_t* __restrict__ planes, int t) {
   const int64_t dd = int64_t(1) << (2 * t);
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
-    const double2 x = X[e];
-    const float2 c = XE[e];
-    const double2 o = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
-    out[e] = o;
-    if (F16)
-      split_value_f16(o, planes, t, e);
-    else
+  if constexpr (F16) {
+    // four consecutive elements per thread (d >= 32)
+    for (int64_t e0 = 4 * (blockIdx.x * int64_t(kThreads) + threadIdx.x); e0 < dd;
+         e0 += 4 * int64_t(gridDim.x) * kThreads) {
+      double2 o[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 x = X[e0 + i];
+        const float2 c = XE[e0 + i];
+        o[i] = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
+        out[e0 + i] = o[i];
+      }
+      split4_f16(o, planes, t, e0);
+    }
+  } else {
+    for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads) {
+      const double2 x = X[e];
+      const float2 c = XE[e];
+      const double2 o = make_double2(x.x - 0.5 * double(c.x), x.y - 0.5 * double(c.y));
+      out[e] = o;
       split_value(o, planes, t, e);
+    }
   }
 }
 
@@ -418,8 +458,19 @@ template <bool F16>
 __global__ void __launch_bounds__(kThreads) k_split_pieces(const double2* __restrict__ V, uint16_t* __restrict__ planes,
                                                            int t) {
   const int64_t dd = int64_t(1) << (2 * t);
-  for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
-    split_entry(V, planes, t, e, false, F16);
+  if constexpr (F16) {
+    // four consecutive elements per thread (d >= 32)
+    for (int64_t e0 = 4 * (blockIdx.x * int64_t(kThreads) + threadIdx.x); e0 < dd;
+         e0 += 4 * int64_t(gridDim.x) * kThreads) {
+      double2 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = V[e0 + i];
+      split4_f16(v, planes, t, e0);
+    }
+  } else {
+    for (int64_t e = blockIdx.x * int64_t(kThreads) + threadIdx.x; e < dd; e += int64_t(gridDim.x) * kThreads)
+      split_entry(V, planes, t, e, false, false);
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_state_scale(const double2* __restrict__ psi, int n, int t,
@@ -721,7 +772,17 @@ __global__ void __launch_bounds__(kThreads) kb_elementwise(int kind, int step, c
       uint16_t* planes = reinterpret_cast<uint16_t*>(D.ws + L.planes);
       const bool f16 = (bflags & kBatchF16) != 0;
       int64_t e0 = local * kSplitTile, e1 = min(e0 + int64_t(kSplitTile), int64_t(d) * d);
-      for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e, false, f16);
+      if (f16) {
+        // four consecutive elements per thread (d >= 32)
+        for (int64_t e = e0 + 4 * threadIdx.x; e < e1; e += 4 * kThreads) {
+          double2 v[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = V[e + i];
+          split4_f16(v, planes, t, e);
+        }
+      } else {
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) split_entry(V, planes, t, e, false, false);
+      }
       break;
     }
     case BK_SCALE:
@@ -814,7 +875,7 @@ hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* o
                                   hipStream_t s, bool f16) {
   int64_t dd = int64_t(1) << (2 * t);
   if (f16)
-    hipLaunchKernelGGL(k_ns_update_split<true>, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
+    hipLaunchKernelGGL(k_ns_update_split<true>, dim3(grid_for(dd / 4)), dim3(kThreads), 0, s, X, XE, out, planes, t);
   else
     hipLaunchKernelGGL(k_ns_update_split<false>, dim3(grid_for(dd)), dim3(kThreads), 0, s, X, XE, out, planes, t);
   return hipGetLastError();
@@ -823,7 +884,7 @@ hipError_t launch_ns_update_split(const double2* X, const float2* XE, double2* o
 hipError_t launch_split_pieces(const double2* V, uint16_t* planes, int t, hipStream_t s, bool f16) {
   int64_t dd = int64_t(1) << (2 * t);
   if (f16)
-    hipLaunchKernelGGL(k_split_pieces<true>, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
+    hipLaunchKernelGGL(k_split_pieces<true>, dim3(grid_for(dd / 4)), dim3(kThreads), 0, s, V, planes, t);
   else
     hipLaunchKernelGGL(k_split_pieces<false>, dim3(grid_for(dd)), dim3(kThreads), 0, s, V, planes, t);
   return hipGetLastError();
