@@ -360,18 +360,20 @@ enum {
   QPE_KERNEL_BATCH_GEMM = 4, /* grouped FP64 power-chain products: 1 32x32
                                 tiles (default), 2 64x64 tiles for d >= 64 */
   QPE_KERNEL_BATCH_SCHED = 5, /* schedule of a batched run with the polar
-                                 step: 1 one stream, 2 (default) the power
+                                 step, and of a single run's prefix-doubling
+                                 form: 1 one stream, 2 (default) the power
                                  chain on a second stream of the context
                                  (created with its events by qpe_ctx_create;
-                                 if that failed, by the first batched run), so
-                                 that the squares and Gram products of step
-                                 k+1 overlap the controlled products of step
-                                 k; joined back into the context stream before
-                                 the run returns, also when it fails. While
-                                 per-kernel timers record (timing enabled and
-                                 a non-empty timing mask), or in
+                                 if that failed, by the first such run), so
+                                 that the power products of step k+1 overlap
+                                 the controlled products of step k; joined
+                                 back into the context stream before the run
+                                 returns, also when it fails. While the
+                                 power-chain timer class records (timing
+                                 enabled and QPE_TIMER_POWERS in the mask:
+                                 its events go to the context stream), or in
                                  qpe_run_static (which creates nothing), one
-                                 stream. */
+                                 stream. The setting of n_mat 0 applies. */
   QPE_KERNEL_COUNT = 6
 };
 qpe_status qpe_kernel_variants(int kernel_class, int *count);

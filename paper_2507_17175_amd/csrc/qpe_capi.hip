@@ -270,10 +270,14 @@ struct TimerScope {
 // into BF16 pieces, three piece pairs (E is O(defect), so the product's
 // error is O(1e-5 defect), far below the FP64 rounding of X), accumulated
 // in FP32 into g, which E no longer needs by then.
+// s: the stream (null: the context's); before_update (optional): an event
+// the stream waits for after the square and the Gram product, before the
+// Newton-Schulz stages write `out` and the planes.
 qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq, double2* g, double2* out,
                             bool polar, unsigned long long* defect, uint16_t* planes = nullptr,
-                            double2* g2 = nullptr, bool* planes_hold_out = nullptr, bool f16 = false) {
-  hipStream_t s = ctx->stream;
+                            double2* g2 = nullptr, bool* planes_hold_out = nullptr, bool f16 = false,
+                            hipStream_t stream = nullptr, hipEvent_t before_update = nullptr) {
+  hipStream_t s = stream ? stream : ctx->stream;
   const int tz = 31 - __builtin_clz(unsigned(d));  // log2 d
   ZgemmArgs a{};
   a.M = a.N = a.K = d;
@@ -298,6 +302,7 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
     QPE_HIP(ctx, launch_gram_split(sq, g, g2, tz, s));
   else
     QPE_HIP(ctx, launch_zgemm(2, 0, h, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));
+  if (before_update) QPE_HIP(ctx, hipStreamWaitEvent(s, before_update, 0));
   double2* gs = gram_split(tz) ? g2 : nullptr;
   if (planes && tz >= 5) {
     // E = G - I with the defect, X -> complex64 and the split of conj(E) in
@@ -392,9 +397,25 @@ qpe_status rotate_target(qpe_ctx* ctx, int t, const double2* U, const double2* p
   return QPE_OK;
 }
 
+// Events of one run of the two-stream schedule: at most two hops per step
+// plus the fork and the join, so no event is recorded twice in one run.
+constexpr int kSchedEvents = 2 * QPE_MAX_N_MEAS + 4;
+
+// The second stream and `nev` events of the two-stream schedule.
+qpe_status ensure_sched(qpe_ctx* ctx, int nev) {
+  if (!ctx->aux) QPE_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  while (int(ctx->sched_ev.size()) < nev) {
+    hipEvent_t e = nullptr;
+    QPE_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->sched_ev.push_back(e);
+  }
+  return QPE_OK;
+}
+
 // keep_state: leave the final state (after the inverse QFT) in state0.
+// allow_aux: the prefix-doubling form may use the two-stream schedule.
 qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags, char* ws, qpe_report* report,
-                   bool keep_state = false) {
+                   bool keep_state = false, bool allow_aux = true) {
   const int n = p.n_meas, t = p.n_mat, d = 1 << t;
   const bool mixed = form == QPE_FORM_MIXED;
   const bool polar = !(flags & QPE_NO_POLAR);
@@ -437,17 +458,60 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     TimerScope ts(ctx, QPE_TIMER_HLAYER);
     QPE_HIP(ctx, launch_h_broadcast(mixed, psi0, s0, n, t, s, dbl));
   }
+  // Prefix-doubling form: the power chain runs on the context's second
+  // stream, one step ahead of the controlled products, most of which are
+  // small (step k has 2^k rows), so the squarings overlap them. Power step k
+  // writes the buffer that held V_{k-2} (so it waits for controlled step
+  // k-2) and, with a Newton-Schulz correction, also V_{k-1}'s buffer and the
+  // operator planes (waiting for controlled step k-1 before those stages);
+  // controlled step k waits for power step k. One stream while the power
+  // chain's timer class records (its events go to the context stream),
+  // without allow_aux (qpe_run_static), or with the one-stream schedule
+  // variant.
+  const bool timers = ctx->timing && ((ctx->timer_mask >> QPE_TIMER_POWERS) & 1u);
+  const bool pipe = dbl && allow_aux && n >= 2 && !timers && ctx->variant[QPE_KERNEL_BATCH_SCHED][0] != 1;
+  hipEvent_t ctrl_done[QPE_MAX_N_MEAS] = {};
+  int next_ev = 0;
+  bool aux_open = false;  // the second stream has work the context stream has not waited for
+  auto mark = [&](hipStream_t on, hipEvent_t* out) -> qpe_status {
+    hipEvent_t e = ctx->sched_ev[size_t(next_ev++) % ctx->sched_ev.size()];
+    QPE_HIP(ctx, hipEventRecord(e, on));
+    *out = e;
+    return QPE_OK;
+  };
+  if (pipe) {
+    qpe_status st = ensure_sched(ctx, kSchedEvents);
+    if (st != QPE_OK) return st;
+    hipEvent_t fork;
+    if ((st = mark(s, &fork)) != QPE_OK) return st;  // after the rotation and the H layer
+    QPE_HIP(ctx, hipStreamWaitEvent(ctx->aux, fork, 0));
+  }
   const double2* cur = U0;
+  qpe_status loop_st = [&]() -> qpe_status {
   for (int k = 0; k < n; ++k) {
     bool planes_ready = false;  // the Newton-Schulz update already split V_k
     if (k > 0) {
       double2* sq = (cur == A) ? B : A;
       double2* other = (sq == A) ? B : A;
       const bool pk = polar && ns_step(k, n);  // this power gets the correction
+      hipStream_t sp = pipe ? ctx->aux : s;
+      hipEvent_t before_update = nullptr;
+      if (pipe) {
+        if (k >= 2) QPE_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctrl_done[k - 2], 0));
+        if (pk) before_update = ctrl_done[k - 1];
+        aux_open = true;
+      }
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes, G2, &planes_ready, f16);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes, G2, &planes_ready, f16, sp,
+                                       before_update);
       if (st != QPE_OK) return st;
       cur = pk ? other : sq;
+      if (pipe) {
+        hipEvent_t done;
+        if ((st = mark(ctx->aux, &done)) != QPE_OK) return st;
+        QPE_HIP(ctx, hipStreamWaitEvent(s, done, 0));
+        aux_open = false;
+      }
     }
     qpe_status st;
     if (dbl) {
@@ -460,6 +524,18 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
                       f16 ? sigma : nullptr);
     }
     if (st != QPE_OK) return st;
+    if (pipe && (st = mark(s, &ctrl_done[k])) != QPE_OK) return st;
+  }
+  return QPE_OK;
+  }();
+  if (loop_st != QPE_OK) {
+    if (aux_open) {
+      // a failed run still leaves the context stream ordered after the work
+      // already enqueued on the second one (best effort, unchecked)
+      hipEvent_t e = ctx->sched_ev[size_t(next_ev) % ctx->sched_ev.size()];
+      if (hipEventRecord(e, ctx->aux) == hipSuccess) (void)hipStreamWaitEvent(s, e, 0);
+    }
+    return loop_st;
   }
   qpe_status st = iqft_and_probs(ctx, mixed, n, t, s0, s1, !dbl, p.prob, reinterpret_cast<double2*>(ws + L.tw_hi),
                                  reinterpret_cast<double2*>(ws + L.tw_lo), keep_state);
@@ -520,21 +596,6 @@ bool state_step(int kind) {
   return kind == BK_SPLIT || kind == BK_CTRL_SMALL || kind == BK_CTRL_M32 || kind == BK_CTRL_M64 ||
          kind == BK_CTRL_M128 || kind == BK_CTRL_M256 || kind == BK_CTRL_F64;
 }
-// Events of one run of the two-stream schedule: at most two hops per step
-// plus the fork and the join, so no event is recorded twice in one run.
-constexpr int kSchedEvents = 2 * QPE_MAX_N_MEAS + 4;
-
-// The second stream and `nev` events of the two-stream schedule.
-qpe_status ensure_sched(qpe_ctx* ctx, int nev) {
-  if (!ctx->aux) QPE_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-  while (int(ctx->sched_ev.size()) < nev) {
-    hipEvent_t e = nullptr;
-    QPE_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ctx->sched_ev.push_back(e);
-  }
-  return QPE_OK;
-}
-
 // allow_aux: the two-stream schedule may be used (it creates the second
 // stream and its events on first use).
 qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, unsigned flags, char* ws,
@@ -588,9 +649,9 @@ qpe_status run_batch(qpe_ctx* ctx, const qpe_problem* p, int count, int form, un
   // state-side launch waits for the chain through step k; the second part
   // of power step k waits for the state side through step k-1 (the plan
   // lists, for each k, the chain's launches before the state's). Per-kernel
-  // timers bracket launches on the context stream, so while any timer class
-  // records, the run keeps one stream.
-  const bool timers = ctx->timing && ctx->timer_mask != 0u;
+  // timers bracket launches on the context stream, so while the power
+  // chain's timer class records, the run keeps one stream.
+  const bool timers = ctx->timing && ((ctx->timer_mask >> QPE_TIMER_POWERS) & 1u);
   const bool pipe = allow_aux && polar && ctx->variant[QPE_KERNEL_BATCH_SCHED][0] != 1 && !timers;
   int next_ev = 0;
   bool forked = false, aux_pending = false;
@@ -1084,7 +1145,8 @@ qpe_status run_checked(qpe_ctx* ctx, const qpe_problem* problems, int count, int
   ctx->last_error.clear();
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
-  if (count == 1) return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report);
+  if (count == 1)
+    return run_one(ctx, problems[0], form, flags, static_cast<char*>(workspace), report, false, allow_aux);
   return run_batch(ctx, problems, count, form, flags, static_cast<char*>(workspace), report, allow_aux);
 }
 }  // namespace

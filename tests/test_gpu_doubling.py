@@ -84,3 +84,42 @@ def test_doubling_batch(qpe, form):
         single = host(qpe.run(U, psi, n, form, flags=qpe.PREFIX_DOUBLING))
         assert np.array_equal(P, single)
         assert np.abs(P - O.fejer(p.phis[0], n)).max() < (1e-6 if form == "mixed" else 1e-10)
+
+
+@pytest.mark.parametrize("form,n,t", [("mixed", 12, 7), ("mixed", 11, 10), ("fp64", 10, 6), ("mixed", 9, 3)])
+def test_single_doubling_two_streams(qpe, form, n, t):
+    """A single run's prefix-doubling form with its power chain on the
+    context's second stream (the default schedule) against the one-stream
+    schedule and the gate route, bit for bit, eagerly and in every replay of
+    its captured graph (the capture forks the second stream and joins it);
+    also with the controlled-product timer recording (the chain stays on the
+    second stream while only that timer class records)."""
+    from paper_2507_17175_amd.qpe import PREFIX_DOUBLING
+    p = make_problem(n, t, np.random.default_rng(8100 + n + t))
+    say("single doubling, two streams", form, n, t)
+    U, psi = dev(p.U), dev(p.psi)
+    gate = host(qpe.run(U, psi, n, form))
+    runner = qpe.Runner([(U, psi, n)], form=form, flags=PREFIX_DOUBLING)
+    ctx = runner.ctx
+    try:
+        ctx.set_variant("batch_sched", 1)
+        one = host(runner()[0]).copy()
+        ctx.set_variant("batch_sched", 2)
+        two = host(runner()[0]).copy()
+        assert np.array_equal(one, gate) and np.array_equal(two, gate)
+        ctx.enable_timing(4096)
+        ctx.set_timing_mask(["ctrl_gemm"])
+        timed = host(runner()[0]).copy()
+        launches, ms = ctx.read_timing()["ctrl_gemm"]
+        assert launches == n and ms > 0
+        assert np.array_equal(timed, gate)
+        ctx.set_timing_mask([])  # timing on, no class recording: two streams
+        graph = qpe.CapturedRun(runner)
+        for rep in range(3):
+            runner.probs[0].fill_(-1.0)
+            host(qpe.run(U, psi, n, form))
+            out = graph()
+            assert np.array_equal(host(out[0]), gate), rep
+    finally:
+        ctx.set_variant("batch_sched", 0)
+        ctx.set_timing_mask([])  # the shared context records no more timer events

@@ -73,6 +73,24 @@ def test_injected_failure_single(qpe, form, at):
     assert np.array_equal(out[0], want)
 
 
+# the prefix-doubling form of a single run puts its power chain on the
+# context's second stream (about 90 checked calls here, event records and
+# waits included); a failure at any of them must leave both streams usable
+@pytest.mark.parametrize("at", [5, 20, 45, 70])
+def test_injected_failure_doubling(qpe, at):
+    from paper_2507_17175_amd.qpe import PREFIX_DOUBLING
+    p = make_problem(10, 7, np.random.default_rng(3050 + at))
+    items = [(torch.from_numpy(p.U).cuda(), torch.from_numpy(p.psi).cuda(), p.n_meas)]
+    want = qpe.run(items[0][0], items[0][1], p.n_meas, "mixed").cpu().numpy()
+    say("fault injected in a prefix-doubling run at", at)
+    ctx = _faulty_context(qpe, at)
+    st, _, err = _run_raw(qpe, ctx, items, "mixed", PREFIX_DOUBLING)
+    assert st == 7 and "injected fault" in err, (st, err)
+    st, out, err = _run_raw(qpe, ctx, items, "mixed", PREFIX_DOUBLING)
+    assert st == 0, err
+    assert np.array_equal(out[0], want)  # bit for bit the gate route's P
+
+
 # the batched run makes about 130 checked calls here (launches, and the event
 # record and wait of each hop between its two streams)
 @pytest.mark.parametrize("at", [1, 4, 30, 60, 90])
