@@ -122,9 +122,10 @@ def test_controlled_step(qpe, form, n, t):
 # From n = 12 (not 17) the readout is summed inside the last DFT pass over
 # column groups of min(d, E) columns (E = 16-64 elements per workgroup):
 # (12, 4), (13, 5), (16, 2) have one group per row, (15, 5) exactly E columns,
-# (12, 7), (15, 6), (14, 8) several partials per row.
+# (12, 7), (15, 6), (14, 8) several partials per row, (16, 0) and (13, 1)
+# one or two columns (no lane exchange, one exchange).
 @pytest.mark.parametrize("n,t", [(1, 0), (3, 2), (4, 1), (5, 3), (8, 0), (9, 2), (12, 4), (13, 5), (16, 2), (17, 1),
-                                 (15, 5), (12, 7), (15, 6), (14, 8)])
+                                 (15, 5), (12, 7), (15, 6), (14, 8), (16, 0), (13, 1)])
 def test_iqft_probs(qpe, form, n, t):
     say("iqft_probs", form, "n", n, "t", t)
     rng = np.random.default_rng(300 + 17 * n + t)
