@@ -107,38 +107,16 @@ __device__ inline void split_value(double2 v, uint16_t* __restrict__ planes, int
   }
 }
 
-// x rounded to the nearest FP16 value, ties to even (|x| below the FP16
-// overflow threshold): the FP16 grid spacing is 2^(e - 10) for |x| in
-// [2^e, 2^(e+1)), e >= -14, and 2^-24 below 2^-14 (subnormals).
-__device__ inline double f16_round(double x) {
-  const double a = fabs(x);
-  if (a < 0x1p-14) return rint(x * 0x1p24) * 0x1p-24;
-  const int e = ilogb(a);
-  // x / q with q = 2^(e - 10), as an exact product by 2^(10 - e)
-  return rint(x * ldexp(1.0, 10 - e)) * ldexp(1.0, e - 10);
-}
-
-__device__ inline uint16_t f16_bits(double exact_f16) {
-  return __builtin_bit_cast(uint16_t, (_Float16)(float)exact_f16);  // exact conversions
-}
-
 // Operator preparation for the split-FP16 controlled GEMM: each FP64
 // component w of V, scaled by 2^kOpScaleLog2F16, is split into two FP16
 // pieces (hi = RNE(w'), lo = RNE(w' - hi)); plane p = 2 piece + component,
 // blocked by 16 columns as the BF16 planes.
 __device__ inline void split_value_f16(double2 v, uint16_t* __restrict__ planes, int t, int64_t e) {
   const int64_t d = int64_t(1) << t;
-  const int64_t dd = d * d;
-  int64_t j = e >> t, c = e & (d - 1);
-  int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
-  double w[2] = {v.x * kOpScaleF16, v.y * kOpScaleF16};
+  uint16_t p[4];
+  split_f16_pieces(v, p);
 #pragma unroll
-  for (int comp = 0; comp < 2; ++comp) {
-    const double hi = f16_round(w[comp]);
-    const double lo = f16_round(w[comp] - hi);
-    planes[(0 * 2 + comp) * dd + dst] = f16_bits(hi);
-    planes[(1 * 2 + comp) * dd + dst] = f16_bits(lo);
-  }
+  for (int pl = 0; pl < 4; ++pl) planes[pl * d * d + plane_offset(d, e >> t, e & (d - 1))] = p[pl];
 }
 
 // The same for the four columns c .. c+3 (c a multiple of 4, d >= 4) of one
@@ -147,19 +125,14 @@ __device__ inline void split_value_f16(double2 v, uint16_t* __restrict__ planes,
 __device__ inline void split4_f16(const double2 (&v)[4], uint16_t* __restrict__ planes, int t, int64_t e0) {
   const int64_t d = int64_t(1) << t;
   const int64_t dd = d * d;
-  const int64_t j = e0 >> t, c = e0 & (d - 1);
-  const int64_t dst = (((c >> 4) * d + j) << 4) + (c & 15);
+  const int64_t dst = plane_offset(d, e0 >> t, e0 & (d - 1));
   uint16_t p[4][4];  // [plane][column]
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const double w[2] = {v[i].x * kOpScaleF16, v[i].y * kOpScaleF16};
+    uint16_t q[4];
+    split_f16_pieces(v[i], q);
 #pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-      const double hi = f16_round(w[comp]);
-      const double lo = f16_round(w[comp] - hi);
-      p[comp][i] = f16_bits(hi);
-      p[2 + comp][i] = f16_bits(lo);
-    }
+    for (int pl = 0; pl < 4; ++pl) p[pl][i] = q[pl];
   }
 #pragma unroll
   for (int pl = 0; pl < 4; ++pl)

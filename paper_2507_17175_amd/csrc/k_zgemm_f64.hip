@@ -250,6 +250,16 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
           if (a.herm && gi > gj) continue;
           a.C[int64_t(gi) * a.ldc + gj] = o;
           if (a.herm && gi < gj) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
+          if (a.planes) {
+            // the operator split of the next controlled step, from the
+            // values just stored (lanes of one row write 16 contiguous
+            // entries of a plane)
+            uint16_t q[4];
+            split_f16_pieces(o, q);
+            const int64_t dd = int64_t(a.N) * a.N, off = plane_offset(a.N, gi, gj);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) a.planes[pl * dd + off] = q[pl];
+          }
         }
       }
 }

@@ -58,16 +58,19 @@ using namespace qpe;
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
 
-RunLayout run_layout(int n, int t, int form, unsigned flags) {
-  return qpe::run_layout(n, t, form == QPE_FORM_MIXED, !(flags & QPE_NO_POLAR));
-}
-
 // The controlled products of the mixed form run as split-FP16 products
 // (three FP16 products per real one) unless QPE_SPLIT_BF16 asks for the
 // six-product BF16 scheme; the FP16 scaling needs the row norms a unitary U
 // keeps, so without the polar step the BF16 scheme runs.
 bool use_f16(int form, unsigned flags) {
   return form == QPE_FORM_MIXED && !(flags & QPE_NO_POLAR) && !(flags & QPE_SPLIT_BF16);
+}
+
+// (A batch lays out its instances with the same sizes; its grouped kernels
+// never use the second plane set.)
+RunLayout run_layout(int n, int t, int form, unsigned flags) {
+  return qpe::run_layout(n, t, form == QPE_FORM_MIXED, !(flags & QPE_NO_POLAR),
+                         (flags & QPE_PREFIX_DOUBLING) && use_f16(form, flags));
 }
 
 int rot_mode(unsigned flags) {
@@ -270,6 +273,9 @@ struct TimerScope {
 // into BF16 pieces, three piece pairs (E is O(defect), so the product's
 // error is O(1e-5 defect), far below the FP64 rounding of X), accumulated
 // in FP32 into g, which E no longer needs by then.
+// With planes, the Newton-Schulz update also splits its result into them,
+// and with split-FP16 products so does the square's epilogue when there is
+// no correction; *planes_hold_out is then set.
 // s: the stream (null: the context's); before_update (optional): an event
 // the stream waits for after the square and the Gram product, before the
 // Newton-Schulz stages write `out` and the planes.
@@ -289,8 +295,14 @@ qpe_status square_and_polar(qpe_ctx* ctx, int d, const double2* cur, double2* sq
   a.beta = make_double2(0.0, 0.0);
   a.C = sq;
   a.ldc = d;
+  // Without a correction the square is the next operator: with split-FP16
+  // products its epilogue also writes the planes.
+  const bool fuse_split = !polar && planes && f16 && tz >= 5;
+  if (fuse_split) a.planes = planes;
   QPE_HIP(ctx, launch_zgemm(0, 0, a, s, ctx->variant[QPE_KERNEL_ZGEMM][tz]));
+  if (fuse_split && planes_hold_out) *planes_hold_out = true;
   if (!polar) return QPE_OK;
+  a.planes = nullptr;
   ZgemmArgs h = a;
   h.A = sq;
   h.B = sq;
@@ -427,7 +439,7 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   double2* B = reinterpret_cast<double2*>(ws + L.tbuf);
   double2* G = polar ? reinterpret_cast<double2*>(ws + L.gbuf) : nullptr;
   double2* G2 = (polar && gram_split(t)) ? reinterpret_cast<double2*>(ws + L.gbuf2) : nullptr;
-  uint16_t* planes = (mixed && t >= 5) ? reinterpret_cast<uint16_t*>(ws + L.planes) : nullptr;
+  uint16_t* planes0 = (mixed && t >= 5) ? reinterpret_cast<uint16_t*>(ws + L.planes) : nullptr;
   unsigned long long* defect = reinterpret_cast<unsigned long long*>(ws + L.scratch);
   const double2* psi = static_cast<const double2*>(p.psi);
 
@@ -450,6 +462,13 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
     psi0 = pr;
   }
   const bool f16 = use_f16(form, flags) && t >= 5;
+  // The operator planes of step k. The prefix-doubling form with split-FP16
+  // products alternates two sets by the parity of k: every power from V_1 on
+  // is split on the power chain's stream (by the square's epilogue or the
+  // Newton-Schulz update), so power step k, which writes set k & 1, only has
+  // to wait for controlled step k-2, the last reader of that set.
+  const bool par = dbl && f16;
+  auto planes_of = [&](int k) { return par && (k & 1) ? reinterpret_cast<uint16_t*>(ws + L.planes2) : planes0; };
   float* sigma = reinterpret_cast<float*>(defect + kScratchSigma);
   if (f16) QPE_HIP(ctx, launch_state_scale(psi0, n, t, sigma, s));
   {
@@ -461,10 +480,12 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   // Prefix-doubling form: the power chain runs on the context's second
   // stream, one step ahead of the controlled products, most of which are
   // small (step k has 2^k rows), so the squarings overlap them. Power step k
-  // writes the buffer that held V_{k-2} (so it waits for controlled step
-  // k-2) and, with a Newton-Schulz correction, also V_{k-1}'s buffer and the
-  // operator planes (waiting for controlled step k-1 before those stages);
-  // controlled step k waits for power step k. One stream while the power
+  // writes the buffer that held V_{k-2} and the planes of step k (so it waits
+  // for controlled step k-2) and, with a Newton-Schulz correction, also
+  // V_{k-1}'s buffer: those stages wait for controlled step k-1 where that
+  // step reads V_{k-1} itself or its split runs on the context stream (one
+  // plane set, d <= 16, the FP64 form, and V_0 at k = 1); controlled step k
+  // waits for power step k. One stream while the power
   // chain's timer class records (its events go to the context stream),
   // without allow_aux (qpe_run_static), or with the one-stream schedule
   // variant.
@@ -498,12 +519,12 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       hipEvent_t before_update = nullptr;
       if (pipe) {
         if (k >= 2) QPE_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctrl_done[k - 2], 0));
-        if (pk) before_update = ctrl_done[k - 1];
+        if (pk && !(par && k >= 2)) before_update = ctrl_done[k - 1];
         aux_open = true;
       }
       TimerScope ts(ctx, QPE_TIMER_POWERS);
-      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes, G2, &planes_ready, f16, sp,
-                                       before_update);
+      qpe_status st = square_and_polar(ctx, d, cur, sq, G, other, pk, defect, planes_of(k), G2, &planes_ready, f16,
+                                       sp, before_update);
       if (st != QPE_OK) return st;
       cur = pk ? other : sq;
       if (pipe) {
@@ -518,9 +539,10 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
       // rows [0, 2^k) of s0 -> rows [2^k, 2^(k+1)) of s0: 2^k outputs, as a
       // "register" of k+1 qubits whose second buffer starts at row 2^k.
       char* upper = static_cast<char*>(s0) + (size_t(1) << k) * size_t(d) * amp;
-      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes, kDoubling, !planes_ready, f16 ? sigma : nullptr);
+      st = controlled(ctx, mixed, k + 1, t, k, cur, s0, upper, planes_of(k), kDoubling, !planes_ready,
+                      f16 ? sigma : nullptr);
     } else {
-      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes, (uint64_t(1) << k) - 1, !planes_ready,
+      st = controlled(ctx, mixed, n, t, k, cur, s0, s1, planes0, (uint64_t(1) << k) - 1, !planes_ready,
                       f16 ? sigma : nullptr);
     }
     if (st != QPE_OK) return st;

@@ -167,16 +167,55 @@ constexpr int kScratchDefect = 0, kScratchKey = 1, kScratchPeak = 2, kScratchSig
 // its split (entries of a unitary operator are at most 1 in magnitude).
 constexpr int kOpScaleLog2F16 = 14;
 constexpr double kOpScaleF16 = double(1 << kOpScaleLog2F16);
+
+// x rounded to the nearest FP16 value, ties to even (|x| below the FP16
+// overflow threshold): the FP16 grid spacing is 2^(e - 10) for |x| in
+// [2^e, 2^(e+1)), e >= -14, and 2^-24 below 2^-14 (subnormals).
+__device__ inline double f16_round(double x) {
+  const double a = fabs(x);
+  if (a < 0x1p-14) return rint(x * 0x1p24) * 0x1p-24;
+  const int e = ilogb(a);
+  // x / q with q = 2^(e - 10), as an exact product by 2^(10 - e)
+  return rint(x * ldexp(1.0, 10 - e)) * ldexp(1.0, e - 10);
+}
+
+__device__ inline uint16_t f16_bits(double exact_f16) {
+  return __builtin_bit_cast(uint16_t, (_Float16)(float)exact_f16);  // exact conversions
+}
+
+// The split-FP16 pieces of one operator entry v: each FP64 component w,
+// scaled by kOpScaleF16, becomes hi = RNE(w) and lo = RNE(w - hi) in FP16;
+// p[2 piece + component].
+__device__ inline void split_f16_pieces(double2 v, uint16_t (&p)[4]) {
+  const double w[2] = {v.x * kOpScaleF16, v.y * kOpScaleF16};
+#pragma unroll
+  for (int comp = 0; comp < 2; ++comp) {
+    const double hi = f16_round(w[comp]);
+    const double lo = f16_round(w[comp] - hi);
+    p[comp] = f16_bits(hi);
+    p[2 + comp] = f16_bits(lo);
+  }
+}
+
+// Offset of entry (j, c) of a d x d operator in one of its split planes,
+// which are blocked by 16 columns: block c / 16 holds rows 0 .. d-1 of those
+// columns, each row's 16 entries contiguous.
+__host__ __device__ inline int64_t plane_offset(int64_t d, int64_t j, int64_t c) {
+  return (((c >> 4) * d + j) << 4) + (c & 15);
+}
 constexpr int kRotHashBlocks = 256;
 constexpr int kRotHashChunk = 4096;  // operator elements per hash chunk
 constexpr size_t kScratchBytes = (kScratchHash + kRotHashBlocks) * 8;
 
 // Regions of one instance's workspace (byte offsets from its base).
 struct RunLayout {
-  size_t state0, state1, vbuf, tbuf, gbuf, gbuf2, planes, tw_hi, tw_lo, scratch, total;
+  size_t state0, state1, vbuf, tbuf, gbuf, gbuf2, planes, tw_hi, tw_lo, scratch, planes2, total;
 };
 
-__host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool polar) {
+// planes2: a second set of operator planes after every other region (so the
+// offsets of the others do not depend on it), for single prefix-doubling runs
+// with split-FP16 products, which alternate the two sets by step parity.
+__host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool polar, bool planes2 = false) {
   RunLayout L{};
   const size_t d = size_t(1) << t, N = size_t(1) << n;
   const size_t amp = mixed ? 8 : 16;
@@ -203,6 +242,8 @@ __host__ __device__ inline RunLayout run_layout(int n, int t, bool mixed, bool p
   off = align_up(off + (size_t(1) << h) * 16);
   L.scratch = off;
   off = align_up(off + kScratchBytes);
+  L.planes2 = off;
+  if (planes2 && mixed && t >= 5) off = align_up(off + 6 * d * d * 2);
   L.total = off;
   return L;
 }
@@ -593,6 +634,10 @@ struct ZgemmArgs {
   // Hermitian result (op(A) = B^H, alpha real, beta 0): only tiles on or
   // above the diagonal are computed; each mirrors itself below it.
   int herm;
+  // When set (a square product, M = N = ldc, herm 0): the epilogue also
+  // writes the split-FP16 pieces of every entry of C (split_f16_pieces) to
+  // the four planes, d^2 entries each, at plane_offset(N, row, column).
+  uint16_t* planes;
 };
 hipError_t launch_zgemm(int opA, int opB, const ZgemmArgs& a, hipStream_t s, int variant);
 int zgemm_variants();
