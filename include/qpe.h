@@ -319,7 +319,9 @@ qpe_status qpe_zgemm(qpe_ctx *ctx, char opA, char opB, int M, int N, int K,
 enum {
   QPE_TIMER_CTRL_GEMM = 0, /* controlled-step kernels (all forms)          */
   QPE_TIMER_POWERS = 1,    /* FP64 squaring and Newton-Schulz kernels       */
-  QPE_TIMER_SPLIT = 2,     /* operator split into BF16 planes              */
+  QPE_TIMER_SPLIT = 2,     /* separate operator-split passes (a split made
+                              in the square's epilogue or the Newton-Schulz
+                              update is timed with the power chain)        */
   QPE_TIMER_QFT = 3,       /* inverse-DFT passes                           */
   QPE_TIMER_PROB = 4,      /* readout                                      */
   QPE_TIMER_HLAYER = 5,    /* Hadamard layer                               */
