@@ -68,6 +68,27 @@ def test_workspace_size(L):
     assert out.value <= mixed + small + (1 << 20)
 
 
+def test_workspace_second_plane_set(L):
+    """A single prefix-doubling run with split-FP16 products (mixed form with
+    the polar step, d >= 32) holds a second set of operator planes, six
+    d x d 16-bit planes, after its other regions; no other run does."""
+    out = ctypes.c_size_t()
+
+    def need(n, t, form, flags):
+        assert L.qpe_workspace_size(_problems([(n, t)]), 1, form, flags, ctypes.byref(out)) == 0
+        return out.value
+
+    dbl, no_polar, bf16 = 2, 1, 16
+    for n, t in [(9, 5), (13, 8), (16, 10)]:
+        d = 1 << t
+        extra = -(-6 * d * d * 2 // 256) * 256
+        assert need(n, t, 1, dbl) - need(n, t, 1, 0) == extra
+        assert need(n, t, 0, dbl) == need(n, t, 0, 0)
+        assert need(n, t, 1, dbl | no_polar) == need(n, t, 1, no_polar)
+        assert need(n, t, 1, dbl | bf16) == need(n, t, 1, bf16)
+    assert need(9, 4, 1, dbl) == need(9, 4, 1, 0)
+
+
 @pytest.mark.parametrize("n,t,code", [(0, 2, 2), (31, 2, 2), (8, -1, 2), (8, 16, 2), (30, 10, 2), (20, 14, 0)])
 def test_size_limits(L, n, t, code):
     out = ctypes.c_size_t()

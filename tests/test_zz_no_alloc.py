@@ -71,6 +71,25 @@ def test_static_matches_run_two_calls(qpe, form):
         assert np.abs(Ps - O.qpe_probs(U, psi, n)).max() < tol
 
 
+def test_static_doubling_two_plane_sets(qpe):
+    """The prefix-doubling form in the static array (one stream there), whose
+    split-FP16 operator planes alternate between two sets: the same P as
+    qpe_run's two-stream schedule and as the gate route, bit for bit."""
+    flags = qpe.PREFIX_DOUBLING
+    for n, t, seed in [(13, 8, 3), (9, 5, 4)]:
+        U, psi, n = _general(n, t, 1550 + seed)
+        need = qpe.workspace_bytes([(n, t)], "mixed", flags)
+        say("static doubling", "n", n, "t", t, "workspace", need)
+        assert need <= qpe.STATIC_WORKSPACE_BYTES
+        Ud, pd = dev(U), dev(psi)
+        Ps = host(qpe.run_batch_static([(Ud, pd, n)], "mixed", flags=flags)[0])
+        Pr = host(qpe.run_batch([(Ud, pd, n)], "mixed", flags=flags)[0])
+        Pg = host(qpe.run_batch([(Ud, pd, n)], "mixed")[0])
+        assert np.array_equal(Ps, Pr)
+        assert np.array_equal(Ps, Pg)
+        assert np.abs(Ps - O.qpe_probs(U, psi, n)).max() < 1e-6
+
+
 def test_static_batch_then_single(qpe):
     """A batched call (uneven instances), then a single smaller instance."""
     probs = [make_problem(n, t, np.random.default_rng(1600 + i))
