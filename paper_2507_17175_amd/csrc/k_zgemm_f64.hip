@@ -48,6 +48,61 @@ __device__ inline int2 xcd_tile_of(int w, int tiles_m, int tiles_n) {
   return make_int2(w / tiles_n, w % tiles_n);
 }
 
+// Epilogue of a wave's FM x FN blocks of 16 x 16 outputs whose first row and
+// column are row0 and col0: re = t1 - t2, im = t3 - t1 - t2, then alpha, beta,
+// the Hermitian mirror, the gather mapping or the operator planes.
+template <bool GATHER, int FM, int FN>
+__device__ __forceinline__ void zgemm_epilogue(const ZgemmArgs& a, const GatherArgs& g,
+                                               const f64x4 (&acc_t1)[FM][FN], const f64x4 (&acc_t2)[FM][FN],
+                                               const f64x4 (&acc_t3)[FM][FN], int row0, int col0, int lr, int lk) {
+  // Output layout of the 16x16 f64 MFMA: lane l, element v holds
+  // row 4 * v + l / 16, column l % 16 of the block.
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi = row0 + x * 16 + 4 * v + lk;
+        int gj = col0 + y * 16 + lr;
+        if (gi >= a.M || gj >= a.N) continue;
+        const double t1 = acc_t1[x][y][v], t2 = acc_t2[x][y][v];
+        double re = t1 - t2, im = acc_t3[x][y][v] - t1 - t2;
+        if (GATHER) {
+          int64_t j = step_row(gi, g.k, g.pmask);
+          double2* dst = pick(g, 1 - src_buffer(j, g.pmask));
+          dst[j * a.ldc + gj] = make_double2(re, im);
+        } else {
+          double2 o;
+          o.x = a.alpha.x * re - a.alpha.y * im;
+          o.y = a.alpha.x * im + a.alpha.y * re;
+          if (a.beta.x != 0.0 || a.beta.y != 0.0) {
+            double2 c = a.Cin[int64_t(gi) * a.ldcin + gj];
+            o.x += a.beta.x * c.x - a.beta.y * c.y;
+            o.y += a.beta.x * c.y + a.beta.y * c.x;
+          }
+          // Hermitian product: only tiles on or above the diagonal run; an
+          // element below the diagonal is always the conjugate of the one
+          // above it (never computed directly, also inside a diagonal tile),
+          // so the result does not depend on the tile size (the Gauss form
+          // rounds C[i][j] and conj(C[j][i]) differently).
+          if (a.herm && gi > gj) continue;
+          a.C[int64_t(gi) * a.ldc + gj] = o;
+          if (a.herm && gi < gj) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
+          if (a.planes) {
+            // the operator split of the next controlled step, from the
+            // values just stored (lanes of one row write 16 contiguous
+            // entries of a plane)
+            uint16_t q[4];
+            split_f16_pieces(o, q);
+            const int64_t dd = int64_t(a.N) * a.N, off = plane_offset(a.N, gi, gj);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) a.planes[pl * dd + off] = q[pl];
+          }
+        }
+      }
+}
+
 template <int OPA, int OPB, bool GATHER, int BM, int BN, int WM, int WN, int kBK = 16>
 __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs& g, int tile_m, int tile_n) {
   constexpr int kThreads = 64 * WM * WN;
@@ -216,52 +271,7 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmArgs& a, const GatherArgs&
     }
   }
 
-  // Epilogue. Output layout of the 16x16 f64 MFMA: lane l, element v holds
-  // row 4 * v + l / 16, column l % 16 of the block.
-#pragma unroll
-  for (int x = 0; x < FM; ++x)
-#pragma unroll
-    for (int y = 0; y < FN; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int gi = i0 + wi0 + x * 16 + 4 * v + lk;
-        int gj = j0 + wj0 + y * 16 + lr;
-        if (gi >= a.M || gj >= a.N) continue;
-        const double t1 = acc_t1[x][y][v], t2 = acc_t2[x][y][v];
-        double re = t1 - t2, im = acc_t3[x][y][v] - t1 - t2;
-        if (GATHER) {
-          int64_t j = step_row(gi, g.k, g.pmask);
-          double2* dst = pick(g, 1 - src_buffer(j, g.pmask));
-          dst[j * a.ldc + gj] = make_double2(re, im);
-        } else {
-          double2 o;
-          o.x = a.alpha.x * re - a.alpha.y * im;
-          o.y = a.alpha.x * im + a.alpha.y * re;
-          if (a.beta.x != 0.0 || a.beta.y != 0.0) {
-            double2 c = a.Cin[int64_t(gi) * a.ldcin + gj];
-            o.x += a.beta.x * c.x - a.beta.y * c.y;
-            o.y += a.beta.x * c.y + a.beta.y * c.x;
-          }
-          // Hermitian product: only tiles on or above the diagonal run; an
-          // element below the diagonal is always the conjugate of the one
-          // above it (never computed directly, also inside a diagonal tile),
-          // so the result does not depend on the tile size (the Gauss form
-          // rounds C[i][j] and conj(C[j][i]) differently).
-          if (a.herm && gi > gj) continue;
-          a.C[int64_t(gi) * a.ldc + gj] = o;
-          if (a.herm && gi < gj) a.C[int64_t(gj) * a.ldc + gi] = make_double2(o.x, -o.y);
-          if (a.planes) {
-            // the operator split of the next controlled step, from the
-            // values just stored (lanes of one row write 16 contiguous
-            // entries of a plane)
-            uint16_t q[4];
-            split_f16_pieces(o, q);
-            const int64_t dd = int64_t(a.N) * a.N, off = plane_offset(a.N, gi, gj);
-#pragma unroll
-            for (int pl = 0; pl < 4; ++pl) a.planes[pl * dd + off] = q[pl];
-          }
-        }
-      }
+  zgemm_epilogue<GATHER, FM, FN>(a, g, acc_t1, acc_t2, acc_t3, i0 + wi0, j0 + wj0, lr, lk);
 }
 
 // Tile (row, column) of workgroup w among the T (T + 1) / 2 tiles on or above
@@ -474,6 +484,12 @@ hipError_t dispatch_size(const ZgemmArgs& a, hipStream_t s, int variant) {
     else
       variant = t64 * ((a.N + 63) / 64) >= 128 ? 3 : small;
   }
+  // A Hermitian product mirrors inside square tiles only; the rectangular
+  // variants run it on the square tile of their class, so that every
+  // variant gives the same bits (the Gauss form rounds C[i][j] and
+  // conj(C[j][i]) differently, so computing both directly would not).
+  if (a.herm && variant == 4) variant = 3;
+  if (a.herm && variant == 5) variant = 1;
   switch (variant) {
     case 1: return go<OPA, OPB, false, 32, 32, 2, 2>(a, g, s);
     case 2: return go<OPA, OPB, false, 64, 64, 2, 2>(a, g, s);

@@ -64,6 +64,21 @@ def test_ctrl_f64_variants(qpe, n, t):
 
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,t", [(9, 7), (8, 10)])
+def test_zgemm_variants_bitwise(qpe, form, n, t):
+    """Every tile variant of the power-chain GEMM sums each output over K in
+    the same order, through the same MFMA operand layout (the K slab only
+    groups the steps between barriers, and a Hermitian product mirrors the
+    same way at every tile size): the same P bit for bit, at d = 128 and at
+    d = 1024 (where the Gram product takes the stream-K plan)."""
+    p, out = _run_all_variants(qpe, "zgemm", form, n, t, 450 + t)
+    for v, P in out.items():
+        assert np.array_equal(P, out[0]), f"variant {v} differs from the default"
+    ref = O.qpe_probs(p.U, p.psi, n)
+    assert float(np.abs(out[0] - ref).max()) <= (1e-11 if form == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
 def test_zgemm_variants(qpe, form):
     n, t = 9, 7
     p, out = _run_all_variants(qpe, "zgemm", form, n, t, 400)
