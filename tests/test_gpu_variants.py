@@ -54,12 +54,13 @@ def test_ctrl_mixed_variants_prefix_doubling(qpe, n, t, scheme):
         assert float(np.abs(P - ref).max()) <= 1e-6, v
 
 
-@pytest.mark.parametrize("n,t", [(8, 5), (9, 7)])
+@pytest.mark.parametrize("n,t", [(8, 5), (9, 7), (11, 9)])
 def test_ctrl_f64_variants(qpe, n, t):
     p, out = _run_all_variants(qpe, "ctrl_f64", "fp64", n, t, 300 + n + t)
     ref = O.qpe_probs(p.U, p.psi, n)
     for v, P in out.items():
-        assert float(np.abs(P - out[0]).max()) <= 1e-13, v
+        # every tile shape sums each output over K in the same order
+        assert np.array_equal(P, out[0]), v
         assert float(np.abs(P - ref).max()) <= 1e-11, v
 
 
