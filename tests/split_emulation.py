@@ -1,7 +1,7 @@
 """CPU emulation of the mixed form's split products (test infrastructure).
 
 A plain numpy model of the arithmetic the controlled products of the mixed
-form use, to judge a splitting scheme before (and beside) the GPU kernels:
+form use, to evaluate a splitting scheme before (and beside) the GPU kernels:
 
   * split-BF16 x6: each FP32 state component and each FP64 operator
     component as three BF16 pieces (round to nearest even of the running
