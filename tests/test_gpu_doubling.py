@@ -86,7 +86,12 @@ def test_doubling_batch(qpe, form):
         assert np.abs(P - O.fejer(p.phis[0], n)).max() < (1e-6 if form == "mixed" else 1e-10)
 
 
-@pytest.mark.parametrize("form,n,t", [("mixed", 12, 7), ("mixed", 11, 10), ("fp64", 10, 6), ("mixed", 9, 3)])
+# (2, 6): the corrected last power is V_1, whose stages rewrite V_0's buffer
+# (split on the context stream); (11, 10) and (13, 6): an even last step, so
+# the correction writes the first plane set while the odd step before it
+# reads the second
+@pytest.mark.parametrize("form,n,t", [("mixed", 12, 7), ("mixed", 11, 10), ("mixed", 13, 6), ("mixed", 2, 6),
+                                      ("fp64", 10, 6), ("mixed", 9, 3)])
 def test_single_doubling_two_streams(qpe, form, n, t):
     """A single run's prefix-doubling form with its power chain on the
     context's second stream (the default schedule) against the one-stream
