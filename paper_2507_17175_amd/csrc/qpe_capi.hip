@@ -482,10 +482,11 @@ qpe_status run_one(qpe_ctx* ctx, const qpe_problem& p, int form, unsigned flags,
   // small (step k has 2^k rows), so the squarings overlap them. Power step k
   // writes the buffer that held V_{k-2} and the planes of step k (so it waits
   // for controlled step k-2) and, with a Newton-Schulz correction, also
-  // V_{k-1}'s buffer: those stages wait for controlled step k-1 where that
-  // step reads V_{k-1} itself or its split runs on the context stream (one
-  // plane set, d <= 16, the FP64 form, and V_0 at k = 1); controlled step k
-  // waits for power step k. One stream while the power
+  // V_{k-1}'s buffer. Those stages also wait for controlled step k-1 where
+  // V_{k-1} is read on the context stream: by the controlled step itself
+  // (d <= 16, the FP64 form) or by its operator split (the split-BF16
+  // scheme, with one plane set; V_0 at k = 1). Controlled step k waits for
+  // power step k. One stream while the power
   // chain's timer class records (its events go to the context stream),
   // without allow_aux (qpe_run_static), or with the one-stream schedule
   // variant.
