@@ -468,7 +468,8 @@ def main():
     if t >= 5:
         roofline = {
             "kernel": (f"{CTRL_KERNELS.get(ctrl_variant, CTRL_DEFAULT)} (controlled product, split-FP16 x3 on MFMA; "
-                       f"variant {ctrl_variant})"),
+                       f"variant {ctrl_variant}"
+                       + (", the built-in kernel at this size" if ctrl_variant in TRAFFIC_VARIANTS else "") + ")"),
             "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_F16_TFLOPS, 4),
             "executed_frac": round(EXECUTED["split_fp16x3"] * achieved / PEAK_F16_TFLOPS, 4),
